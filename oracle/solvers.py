@@ -41,6 +41,17 @@ def solve_sparse(Mt, Bt, Mx, Ax, F):
     return spla.spsolve(K, F.ravel()).reshape(F.shape)
 
 
+def apply_global_structured(Mt, Bt, Mx, Ax, U):
+    """K vec(U) = vec(i B_t U M_x^T + M_t U A_x^T) without forming the
+    Kronecker product (for large problems).  U: (n_t, n_x) or (k, n_t, n_x)."""
+    U = np.asarray(U)
+    if U.ndim == 3:
+        return np.stack([apply_global_structured(Mt, Bt, Mx, Ax, u) for u in U])
+    UM = (sp.csr_matrix(Mx) @ U.T).T
+    UA = (sp.csr_matrix(Ax) @ U.T).T
+    return 1j * (sp.csr_matrix(Bt) @ UM) + sp.csr_matrix(Mt) @ UA
+
+
 def fdm_paper(Mt, Bt, Mx, Ax, F, return_parts=False):
     """Fast diagonalisation, exactly in the paper's form (Sec. 3, solver steps
     1-4 with the eigenvalue decomposition as the second choice of X_t, S_t):
@@ -50,21 +61,29 @@ def fdm_paper(Mt, Bt, Mx, Ax, F, return_parts=False):
       2. g = (Y_t kron I) f with Y_t = X_t^{-1} (i B_t)^{-1};
       3. (M_x + S_t[l,l] A_x) w_l = g_l for every l, independently;
       4. psi = (X_t kron I) w.
+    F may hold several right-hand sides, shape (k, n_t, n_x); each spatial
+    matrix is then factored once for all of them.
     """
+    F = np.asarray(F)
+    multi = F.ndim == 3
+    Fs = F if multi else F[None]
     iB = 1j * np.asarray(Bt, dtype=np.complex128)
     Mt = np.asarray(Mt, dtype=np.float64)
     A = np.linalg.solve(iB, Mt)
     mu, X = np.linalg.eig(A)
     X = X / np.linalg.norm(X, axis=0)
     Y = np.linalg.solve(X, np.linalg.inv(iB))
-    G = Y @ F
+    G = np.einsum("lm,kmx->klx", Y, Fs)
     Wb = np.empty_like(G)
     Mx = sp.csc_matrix(Mx)
     Ax = sp.csc_matrix(Ax)
-    for l in range(G.shape[0]):
+    for l in range(G.shape[1]):
         lu = spla.splu((Mx + mu[l] * Ax).tocsc())
-        Wb[l] = lu.solve(G[l])
-    psi = X @ Wb
+        for k in range(G.shape[0]):
+            Wb[k, l] = lu.solve(np.ascontiguousarray(G[k, l]))
+    psi = np.einsum("lm,kmx->klx", X, Wb)
+    if not multi:
+        psi = psi[0]
     if return_parts:
         return psi, dict(mu=mu, X=X, Y=Y)
     return psi

@@ -1,0 +1,107 @@
+"""ctypes binding of libstfem.so (include/stfem.h).  Argument marshalling only:
+every step of the solve runs in the library's HIP kernels and host C++.
+
+The library is loaded from this package directory; if it is missing the
+binding raises instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstfem.so")
+
+STATUS = {0: "STFEM_OK", -1: "STFEM_EINVAL", -2: "STFEM_ENOMEM", -3: "STFEM_EHIP", -4: "STFEM_ENOTDIAG",
+          -5: "STFEM_ENOCONV", -6: "STFEM_EBREAKDOWN"}
+ST_ORDER = ("C", "E", "W", "N", "S", "NE", "SW")
+
+
+class StfemError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, message))
+        self.status = status
+        self.message = message
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double), ("kappa_x", ctypes.c_double),
+                ("ms_eig", ctypes.c_double), ("ms_factor", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("ms_band_fill", ctypes.c_double), ("ms_ldlt", ctypes.c_double), ("ms_sweeps", ctypes.c_double),
+                ("ms_transforms", ctypes.c_double), ("ms_residual", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+_SIGS = {
+    "assemble_1d_time": (ctypes.c_int, [ctypes.c_int, _D, ctypes.c_int, _D, _D, _D, _D]),
+    "assemble_2d_space": (ctypes.c_int, [ctypes.c_int, _D, _D, _I, _I]),
+    "fdm_temporal": (ctypes.c_int, [_D, _D, ctypes.c_int, _D, _D, _D, _D, _I]),
+    "fdm_factor": (ctypes.c_int, [_D, _D, ctypes.c_int, _D, _D, ctypes.c_int, ctypes.POINTER(Options), _P,
+                                  ctypes.POINTER(_P)]),
+    "fdm_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, ctypes.POINTER(Report)]),
+    "fdm_solve_adjoint": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, ctypes.POINTER(Report)]),
+    "fdm_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P]),
+    "fdm_decomposition": (ctypes.c_int, [_P, _D, _D, _D, _D]),
+    "fdm_sizes": (ctypes.c_int, [_P, _I, _I, _I, _I]),
+    "fdm_destroy": (None, [_P]),
+    "shifted_factor": (ctypes.c_int, [ctypes.c_int, _D, _D, _D, ctypes.c_int, ctypes.c_int, _P,
+                                      ctypes.POINTER(_P)]),
+    "shifted_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P]),
+    "shifted_factor_band": (ctypes.c_int, [_P, ctypes.c_int, _D]),
+    "shifted_destroy": (None, [_P]),
+    "apply_spatial": (ctypes.c_int, [ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, _P, _P, ctypes.c_int, _P]),
+    "stfem_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "stfem_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libstfem.so is not built (expected at %s); run "
+                              "`python -m paper_2504_07269_amd.build`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def check(status):
+    if status != 0:
+        raise StfemError(status, lib().stfem_last_error().decode())
+    return status
+
+
+def dptr(a):
+    """ctypes double* of a C-contiguous float64 numpy array (or None)."""
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def cptr(a):
+    """ctypes double* of a C-contiguous complex128 numpy array viewed as pairs."""
+    assert a.dtype == np.complex128 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)

@@ -1,0 +1,61 @@
+// Launch wrappers of the HIP kernels (implemented in kernels.hip).  All
+// pointers are device pointers; complex values are interleaved (re, im).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/stfem.h"
+
+namespace stfem {
+namespace gpu {
+
+// 7-point stencils of M_x and A_x in STFEM_ST_* order for n cells per side.
+struct Stencil {
+    double M[7];
+    double A[7];
+    int n;      // cells per side
+    int m;      // grid width n-1; n_x = m*m, kd = n = m+1
+};
+
+// Band storage of one block: band[j*(kd+1) + d] = S[j+d][j], d = 0..kd.
+// S_l = lambda_l M_x + A_x for l in [0, count); lambda: complex128[count].
+hipError_t band_fill(int precision, void* band, const double* lambda, int count, const Stencil& st,
+                     hipStream_t s);
+
+// In-place L D L^T of `count` bands; info[l] = 1 + first bad column (0 = ok).
+hipError_t ldlt_factor(int precision, void* band, int count, const Stencil& st, int* info, hipStream_t s);
+
+// U[r][l] = S_l^{-1} G[r][l] (conj: conj(S_l)^{-1}); G, U complex128
+// [nrhs][count][n_x]; may alias.
+hipError_t sweep_solve(int precision, const void* band, int count, const Stencil& st, const double* G,
+                       double* U, int nrhs, int conj, hipStream_t s);
+
+// C[b] = op(A) B[b] (+ C[b] if accumulate); A complex128 n x n row-major,
+// op = A (trans = 0) or A^H (trans = 1); B[b], C[b] complex128 n x ncols
+// row-major with batch strides strideB, strideC (in complex elements).
+hipError_t zgemm_small_left(int n, int ncols, int batch, const double* A, int trans, const double* B,
+                            long long strideB, double* C, long long strideC, int accumulate, hipStream_t s);
+
+// R = F - K Psi (adjoint = 0) or F - K^H Psi (adjoint = 1), with
+// K = i B_t (x) M_x + M_t (x) A_x; temporal matrices in band storage
+// tM[l*(2w+1) + (m-l+w)], tB[...] (doubles).  Per-rhs squared norms of R and
+// F are accumulated into norms[2*r], norms[2*r+1] (overwritten).
+// Uses `partial` (>= residual_partial_size doubles) as scratch.
+hipError_t kron_residual(const double* Psi, const double* F, double* R, int nrhs, int n_t, int w,
+                         const double* tM, const double* tB, const Stencil& st, int adjoint,
+                         double* partial, double* norms, hipStream_t s);
+size_t residual_partial_size(int nrhs, int n_t, int n_x);
+
+// Y = K Psi or K^H Psi (no F, no norms).
+hipError_t kron_apply(const double* Psi, double* Y, int nrhs, int n_t, int w, const double* tM,
+                      const double* tB, const Stencil& st, int adjoint, hipStream_t s);
+
+// Y_v = (alpha M + beta A) X_v for `count` vectors of n_x.
+hipError_t spatial_apply(const Stencil& st, double ar, double ai, double br, double bi, const double* X,
+                         double* Y, int count, hipStream_t s);
+
+// p[0..count) = value (a kernel, so that it may be recorded in a graph).
+hipError_t fill_int(int* p, int count, int value, hipStream_t s);
+
+}  // namespace gpu
+}  // namespace stfem

@@ -26,3 +26,19 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    # Name the case on stderr before any GPU work starts, so a run that dies
+    # inside a kernel still shows which test, shape and entry point it was.
+    if "gpu" in request.keywords:
+        sys.__stderr__.write("\n[gpu case] %s\n" % request.node.nodeid)
+        sys.__stderr__.flush()
+    yield
+
+
+@pytest.fixture(scope="session")
+def cuda():
+    import torch
+    return torch.device("cuda:0")

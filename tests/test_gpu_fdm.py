@@ -1,0 +1,133 @@
+"""End-to-end parity of the HIP fast-diagonalization path (fdm_factor,
+fdm_solve, fdm_solve_adjoint, fdm_apply) with the CPU oracle.
+
+Bars: on the n=16, N_t=16 workload the FP64 path must equal the oracle's
+dense global LU to 1e-12 relative; every solve must reach the requested
+relative residual ||F - K Psi|| / ||F|| (re-measured with the oracle's own
+Kronecker matvec) of 1e-10; the GPU matvec equals the oracle's to 1e-13."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2504_07269_amd as st
+import synth
+from oracle import fem, problems, solvers
+from gpu_util import relerr, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def system(n, N_t, T=1.0, p=1, nodes=None):
+    if nodes is None:
+        nodes = synth.uniform_nodes(T, N_t)
+    Mt, Bt, m0, b0 = st.assemble_1d_time(nodes, p)
+    Ms, As, n_x, kd = st.assemble_2d_space(n)
+    Mx, Ax = fem.assemble_space(n)
+    return nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax
+
+
+def oracle_rhs_c0(n=16, N_t=16, T=1.0, p=1):
+    """Homogenised load vector of psi_omega (omega = pi) by the oracle's quadrature
+    and its constant-in-time lift."""
+    prob = problems.OmegaSolution(np.pi)
+    nodes = fem.time_nodes_uniform(T, N_t)
+    Mf, _ = fem.assemble_time_full(nodes, p)
+    _, Ax = fem.assemble_space(n)
+    F = fem.load_vector(prob.f, n, nodes, p)
+    psi0 = fem.interpolate(lambda x, y, t: prob.psi0(x, y), n, nodes, p)[0]
+    return solvers.lift_constant(F, psi0, Mf, Ax)
+
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-13), (32, 1e-12)])
+def test_c0_matches_dense_global_lu(precision, tol):
+    nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(16, 16)
+    F = oracle_rhs_c0()
+    ref = solvers.solve_dense(Mt, Bt, Mx, Ax, F)
+    h = st.fdm_factor(Mt, Bt, Ms, As, 16, precision=precision, tol=tol, max_iter=40)
+    Psi = to_host(h.solve(to_dev(F)))
+    assert relerr(Psi, ref) < 1e-12 if precision == 64 else relerr(Psi, ref) < 1e-10
+    assert solvers.relres(Mt, Bt, Mx, Ax, Psi, F) < max(tol, 1e-13) * 2
+    assert h.last_report["rel_residual"] <= tol
+
+
+@pytest.mark.parametrize("p,N_t,graded", [(2, 8, False), (1, 12, True)])
+def test_p2_and_graded_time(p, N_t, graded):
+    nodes = synth.graded_nodes(1.0, N_t, 1.5) if graded else synth.uniform_nodes(1.0, N_t)
+    nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(10, N_t, p=p, nodes=nodes)
+    F = synth.random_rhs(21, Mt.shape[0], 81, 2)
+    h = st.fdm_factor(Mt, Bt, Ms, As, 10, precision=64, tol=1e-13, max_iter=10)
+    Psi = to_host(h.solve(to_dev(F)))
+    for r in range(2):
+        assert relerr(Psi[r], solvers.solve_dense(Mt, Bt, Mx, Ax, F[r])) < 1e-12
+
+
+def test_apply_matches_oracle_matvec():
+    nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(9, 7, p=2)
+    h = st.fdm_factor(Mt, Bt, Ms, As, 9, precision=64, tol=0)
+    U = synth.random_rhs(4, Mt.shape[0], 64, 3)
+    KU = to_host(h.apply(to_dev(U)))
+    KHU = to_host(h.apply(to_dev(U), adjoint=True))
+    K = solvers.global_matrix(Mt, Bt, Mx, Ax)
+    for r in range(3):
+        assert relerr(KU[r], (K @ U[r].ravel()).reshape(U[r].shape)) < 1e-13
+        assert relerr(KHU[r], (K.conj().T @ U[r].ravel()).reshape(U[r].shape)) < 1e-13
+
+
+@pytest.mark.parametrize("precision,tol", [(64, 1e-13), (32, 1e-12)])
+def test_adjoint_matches_dense(precision, tol):
+    nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(16, 16)
+    G = synth.random_rhs(31, 16, 225)
+    ref = solvers.solve_dense_adjoint(Mt, Bt, Mx, Ax, G)
+    h = st.fdm_factor(Mt, Bt, Ms, As, 16, precision=precision, tol=tol, max_iter=40)
+    Lam = to_host(h.solve_adjoint(to_dev(G)))
+    assert relerr(Lam, ref) < (1e-12 if precision == 64 else 1e-10)
+    # dot test <K^{-1} a, b> = <a, K^{-H} b>
+    a = synth.random_rhs(32, 16, 225)
+    x = to_host(h.solve(to_dev(a)))
+    assert abs(np.vdot(G, x) - np.vdot(Lam, a)) < 1e-10 * abs(np.vdot(G, x))
+
+
+def test_no_convergence_is_reported():
+    nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(16, 16)
+    h = st.fdm_factor(Mt, Bt, Ms, As, 16, precision=32, tol=1e-15, max_iter=0)
+    with pytest.raises(st.StfemError) as e:
+        h.solve(to_dev(synth.random_rhs(1, 16, 225)))
+    assert e.value.status == -5
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_c1_five_rhs(precision):
+    """n=128, N_t=128, T=1: the manufactured load plus 4 seeded random loads."""
+    wl = synth.WORKLOADS["c1"]
+    nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(wl.n, wl.N_t, wl.T)
+    F = np.concatenate([synth.manufactured_rhs(wl)[None],
+                        np.stack([synth.random_rhs(s, wl.n_t, wl.n_x) for s in range(4)])])
+    h = st.fdm_factor(Mt, Bt, Ms, As, wl.n, precision=precision, tol=1e-10, max_iter=60)
+    Psi = to_host(h.solve(to_dev(F)))
+    R = F - solvers.apply_global_structured(Mt, Bt, Mx, Ax, Psi)
+    for r in range(5):
+        assert np.linalg.norm(R[r]) / np.linalg.norm(F[r]) <= 1e-10
+    # forward difference to the oracle's paper-form FDM on the manufactured load
+    ref = solvers.fdm_paper(Mt, Bt, Mx, Ax, F[0])
+    assert relerr(Psi[0], ref) < 1e-8
+    # discretisation sanity: close to the nodal values of the exact psi_hat
+    assert relerr(Psi[0], synth.manufactured_psi_hat(wl)) < 1e-2
+
+
+def test_c2_fp32_refined_and_fp64_reach_1e10():
+    """n=256, N_t=256, T=2, omega = 4 pi: the benchmark workload."""
+    wl = synth.WORKLOADS["c2"]
+    nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(wl.n, wl.N_t, wl.T)
+    F = synth.manufactured_rhs(wl)
+    res = {}
+    for precision in (32, 64):
+        h = st.fdm_factor(Mt, Bt, Ms, As, wl.n, precision=precision, tol=1e-10, max_iter=60)
+        Psi = to_host(h.solve(to_dev(F)))
+        res[precision] = (Psi, h.last_report)
+        h.close()
+        torch.cuda.empty_cache()
+        R = F - solvers.apply_global_structured(Mt, Bt, Mx, Ax, Psi)
+        assert np.linalg.norm(R) / np.linalg.norm(F) <= 1e-10
+    # both precisions solve the same system
+    assert relerr(res[32][0], res[64][0]) < 1e-7
+    assert relerr(res[64][0], synth.manufactured_psi_hat(wl)) < 1e-2

@@ -376,3 +376,21 @@ def test_lift_by_t0_hat_equals_constant_lift():
     Fh = F[1:] - (1j * np.outer(bc, Mx @ psi0) + np.outer(mc, Ax @ psi0))
     Uh = solvers.solve_dense(Mt, Bt, Mx, Ax, Fh)
     assert np.abs(Uc - Uh).max() < 1e-12 * np.abs(Uc).max()
+
+
+def test_structured_matvec_matches_kron():
+    _, Mt, Bt, _, _, Mx, Ax = _c0_system(p=2, Nt=4, n=6)
+    rng = np.random.default_rng(8)
+    U = rng.standard_normal((2, 8, 25)) + 1j * rng.standard_normal((2, 8, 25))
+    a = solvers.apply_global_structured(Mt, Bt, Mx, Ax, U)
+    for k in range(2):
+        assert np.abs(a[k] - solvers.apply_global(Mt, Bt, Mx, Ax, U[k])).max() < 1e-14
+
+
+def test_fdm_paper_multiple_rhs():
+    _, Mt, Bt, _, _, Mx, Ax = _c0_system(Nt=5, n=6)
+    rng = np.random.default_rng(9)
+    F = rng.standard_normal((3, 5, 25)) + 1j * rng.standard_normal((3, 5, 25))
+    a = solvers.fdm_paper(Mt, Bt, Mx, Ax, F)
+    for k in range(3):
+        assert np.abs(a[k] - solvers.solve_dense(Mt, Bt, Mx, Ax, F[k])).max() < 1e-12 * np.abs(a[k]).max()
