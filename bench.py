@@ -54,6 +54,11 @@ def measured_traffic(precision):
     return d.get("bytes_per_launch")
 
 
+def progress(msg):
+    sys.stderr.write("[bench] %s\n" % msg)
+    sys.stderr.flush()
+
+
 def run_steps(st, torch, inputs, precision, steps, warmup, tol, max_iter):
     Mt, Bt, Ms, As, n, F = inputs
     reports = []
@@ -65,8 +70,11 @@ def run_steps(st, torch, inputs, precision, steps, warmup, tol, max_iter):
         h.close()
         return Psi, rep
 
-    for _ in range(warmup):
-        one()
+    for i in range(warmup):
+        _, rep = one()
+        progress("fp%d warmup %d: %.1f ms, ldlt %.1f ms, %d refinement passes, residual %.2e"
+                 % (precision, i, rep["ms_total"] + rep["ms_eig"] + rep["ms_factor"], rep["ms_ldlt"],
+                    rep["iterations"], rep["rel_residual"]))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -74,6 +82,7 @@ def run_steps(st, torch, inputs, precision, steps, warmup, tol, max_iter):
         reports.append(rep)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    progress("fp%d: %d timed steps, %.1f ms per step" % (precision, steps, (t1 - t0) * 1000.0 / steps))
     return (t1 - t0) * 1000.0 / steps, reports, Psi
 
 
@@ -99,6 +108,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-block-stride", type=int, default=2)
+    ap.add_argument("--factor-only", type=int, default=0, metavar="PRECISION",
+                    help="profiling aid: run one fdm_factor of the workload in this precision and exit")
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
+                    help="profiling aid: one device-to-device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only; --gpus %d is not supported (the solver is a single-GPU "
@@ -112,6 +125,16 @@ def main():
     import paper_2504_07269_amd as st
     import synth
 
+    if args.copy_probe > 0:
+        nbytes = int(args.copy_probe * 2 ** 30)
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        progress("copied %d bytes" % nbytes)
+        return
+
     wl = synth.WORKLOADS[args.workload]
     if wl.p_t != 1 and wl.n > 256:
         print("workload %s does not fit one GPU unchunked" % wl.name, file=sys.stderr)
@@ -122,6 +145,12 @@ def main():
     F_np = synth.manufactured_rhs(wl)
     F = torch.from_numpy(F_np).to("cuda:0")
     inputs = (Mt, Bt, Ms, As, wl.n, F)
+    if args.factor_only:
+        h = st.fdm_factor(Mt, Bt, Ms, As, wl.n, precision=args.factor_only, tol=args.tol)
+        torch.cuda.synchronize()
+        progress("factor only: fp%d done" % args.factor_only)
+        h.close()
+        return
 
     ms32, reps32, _ = run_steps(st, torch, inputs, 32, args.steps, args.warmup, args.tol, args.max_iter)
     value = wl.dofs / (ms32 / 1000.0)
@@ -159,8 +188,9 @@ def main():
                        "ldlt_tflops": ldlt_flops(n_x, kd) * wl.n_t / (avg(reps64, "ms_ldlt") / 1000) / 1e12}
         out["speedup_fp32ir_vs_fp64"] = value / v64
     if not args.no_cpu_baseline:
-        F_np_local = F_np
-        out["cpu_baseline"] = cpu_baseline(wl, Mt, Bt, F_np_local, args.cpu_block_stride)
+        progress("cpu baseline (oracle FDM on the host cores)")
+        out["cpu_baseline"] = cpu_baseline(wl, Mt, Bt, F_np, args.cpu_block_stride)
+        progress("cpu baseline: %.3g dof/s" % out["cpu_baseline"]["value"])
     print(json.dumps(out))
 
 

@@ -57,11 +57,23 @@ def fdm_timed(Mt, Bt, n, F, workers=None, block_stride=1):
     t2 = time.perf_counter()
     idx = list(range(0, G.shape[0], block_stride))
     ctx = mp.get_context("spawn")
-    with ctx.Pool(workers, initializer=_init, initargs=(n,)) as pool:
-        pool.map(_solve_block, [(mu[0], np.ascontiguousarray(G[0]))])      # start-up, not timed
-        t3 = time.perf_counter()
-        sols = pool.map(_solve_block, [(mu[l], np.ascontiguousarray(G[l])) for l in idx], chunksize=1)
-        t4 = time.perf_counter()
+    # one BLAS thread per worker: several multithreaded BLAS pools on the same
+    # cores spin against each other and slow every sparse LU down many times
+    saved = {k: os.environ.get(k) for k in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        with ctx.Pool(workers, initializer=_init, initargs=(n,)) as pool:
+            pool.map(_solve_block, [(mu[0], np.ascontiguousarray(G[0]))] * workers)   # start-up, not timed
+            t3 = time.perf_counter()
+            sols = pool.map(_solve_block, [(mu[l], np.ascontiguousarray(G[l])) for l in idx], chunksize=1)
+            t4 = time.perf_counter()
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
     psi = None
     t5 = t6 = 0.0
     if block_stride == 1:

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -321,9 +322,12 @@ int solve_common(stfem_handle* h, const void* F_dev, void* Psi_dev, int nrhs, vo
         rep->ms_factor = h->ms_factor;
         rep->ms_total = now_ms() - t0;
     }
-    if (h->opt.tol > 0 && !(rel <= h->opt.tol))
-        return fail(STFEM_ENOCONV, "refinement stopped at relative residual " + std::to_string(rel) + " after " +
-                                       std::to_string(it) + " passes");
+    if (h->opt.tol > 0 && !(rel <= h->opt.tol)) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "refinement stopped at relative residual %.3e (tolerance %.3e) after %d passes",
+                      rel, h->opt.tol, it);
+        return fail(STFEM_ENOCONV, msg);
+    }
     return STFEM_OK;
 }
 
