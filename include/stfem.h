@@ -86,6 +86,8 @@ typedef struct stfem_report {
     double ms_sweeps;       /* all sweep kernels of this call                     */
     double ms_transforms;   /* all temporal-transform GEMM kernels of this call   */
     double ms_residual;     /* all residual kernels of this call                  */
+    double history[16];     /* relative residual after each of the first 16 passes
+                               (unused entries are -1)                             */
 } stfem_report;
 
 typedef struct stfem_handle stfem_handle;   /* FDM solver: X, W, lambda, factors */
@@ -209,6 +211,12 @@ void shifted_destroy(stfem_blocks* b);
 int apply_spatial(int n, const double* M_stencil, const double* A_stencil,
                   double alpha_re, double alpha_im, double beta_re, double beta_im,
                   const void* X_dev, void* Y_dev, int count, void* stream);
+
+/* Factor storage (tens of GB) released by fdm_destroy / shifted_destroy is
+ * kept by the library, at most two buffers per device, and reused by later
+ * factorisations that fit; this returns all of it to the device.  Not to be
+ * called while another thread is inside the library. */
+void stfem_release_cache(void);
 
 /* ------------------------------------------------------------------ errors */
 const char* stfem_strerror(int status);

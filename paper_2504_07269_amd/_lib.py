@@ -32,10 +32,13 @@ class Report(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double), ("kappa_x", ctypes.c_double),
                 ("ms_eig", ctypes.c_double), ("ms_factor", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("ms_band_fill", ctypes.c_double), ("ms_ldlt", ctypes.c_double), ("ms_sweeps", ctypes.c_double),
-                ("ms_transforms", ctypes.c_double), ("ms_residual", ctypes.c_double)]
+                ("ms_transforms", ctypes.c_double), ("ms_residual", ctypes.c_double),
+                ("history", ctypes.c_double * 16)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "history"}
+        d["history"] = [v for v in self.history if v >= 0]
+        return d
 
 
 _lib = None
@@ -62,6 +65,7 @@ _SIGS = {
     "shifted_destroy": (None, [_P]),
     "apply_spatial": (ctypes.c_int, [ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, _P, _P, ctypes.c_int, _P]),
+    "stfem_release_cache": (None, []),
     "stfem_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "stfem_last_error": (ctypes.c_char_p, []),
 }

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -75,6 +76,7 @@ struct stfem_blocks {
     int n = 0, m = 0, n_x = 0, kd = 0, count = 0, precision = 64;
     gpu::Stencil st{};
     void* band = nullptr;
+    size_t band_bytes = 0;
     int* info = nullptr;
     double* lambda_dev = nullptr;
     std::vector<double> lambda;   // host copy, interleaved complex
@@ -104,6 +106,71 @@ struct stfem_handle {
 
 namespace {
 
+// Factor storage runs to tens of GB; allocating and releasing it costs
+// hundreds of milliseconds.  Released factor buffers of >= 64 MiB are kept
+// (at most two per device) and handed to the next factorisation that fits in
+// them without wasting more than a quarter; stfem_release_cache() returns
+// them to the device.
+struct CachedBuffer {
+    void* ptr;
+    size_t bytes;
+    int device;
+};
+std::mutex g_cache_mutex;
+std::vector<CachedBuffer> g_cache;
+constexpr size_t CACHE_MIN_BYTES = (size_t)64 << 20;
+
+void release_cache_locked() {
+    for (auto& c : g_cache) (void)hipFree(c.ptr);
+    g_cache.clear();
+}
+
+hipError_t factor_alloc(void** p, size_t bytes) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mutex);
+        for (size_t i = 0; i < g_cache.size(); ++i) {
+            const CachedBuffer c = g_cache[i];
+            if (c.device == dev && c.bytes >= bytes && c.bytes - bytes <= c.bytes / 4) {
+                g_cache.erase(g_cache.begin() + i);
+                *p = c.ptr;
+                return hipSuccess;
+            }
+        }
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {   // give the cached buffers back and retry once
+        (void)hipGetLastError();
+        std::lock_guard<std::mutex> lk(g_cache_mutex);
+        release_cache_locked();
+        e = hipMalloc(p, bytes);
+    }
+    return e;
+}
+
+void factor_free(void* p, size_t bytes) {
+    if (!p) return;
+    if (bytes < CACHE_MIN_BYTES) {
+        (void)hipFree(p);
+        return;
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_cache_mutex);
+    int same = 0;
+    for (auto& c : g_cache) same += (c.device == dev);
+    if (same >= 2) {   // drop the oldest buffer of this device
+        for (size_t i = 0; i < g_cache.size(); ++i)
+            if (g_cache[i].device == dev) {
+                (void)hipFree(g_cache[i].ptr);
+                g_cache.erase(g_cache.begin() + i);
+                break;
+            }
+    }
+    g_cache.push_back({p, bytes, dev});
+}
+
 bool stencil_ok(const double* Ms, const double* As) {
     for (int q = 0; q < 7; ++q)
         if (!std::isfinite(Ms[q]) || !std::isfinite(As[q])) return false;
@@ -129,7 +196,7 @@ size_t elem_bytes(int precision) { return precision == 32 ? 8 : 16; }
 void free_blocks(stfem_blocks* b) {
     if (!b) return;
     b->timer.release();
-    if (b->band) (void)hipFree(b->band);
+    factor_free(b->band, b->band_bytes);
     if (b->info) (void)hipFree(b->info);
     if (b->lambda_dev) (void)hipFree(b->lambda_dev);
     delete b;
@@ -155,8 +222,9 @@ int blocks_launch(int n, const double* Ms, const double* As, const double* lambd
     b->precision = precision;
     b->st = make_stencil(n, Ms, As);
     b->lambda.assign(lambda, lambda + 2 * count);
-    const size_t bytes = (size_t)count * b->n_x * (b->kd + 1) * elem_bytes(precision);
-    if (hipMalloc(&b->band, bytes) != hipSuccess) {
+    const size_t bytes = (size_t)count * gpu::band_stride_host(n) * elem_bytes(precision);
+    b->band_bytes = bytes;
+    if (factor_alloc(&b->band, bytes) != hipSuccess) {
         (void)hipGetLastError();
         b->band = nullptr;
         free_blocks(b);
@@ -292,6 +360,8 @@ int solve_common(stfem_handle* h, const void* F_dev, void* Psi_dev, int nrhs, vo
     if (st) return st;
     int it = 0;
     double rel = -1.0;
+    double hist[16];
+    for (double& x : hist) x = -1.0;
     if (h->opt.tol > 0) {
         for (;;) {
             HIPCHECK(h->timer.begin(s));
@@ -300,6 +370,7 @@ int solve_common(stfem_handle* h, const void* F_dev, void* Psi_dev, int nrhs, vo
             HIPCHECK(h->timer.end(s, StageTimer::RESID));
             st = read_relres(h, nrhs, s, rel);
             if (st) return st;
+            if (it < 16) hist[it] = rel;
             if (rel <= h->opt.tol || it >= h->opt.max_iter || !std::isfinite(rel)) break;
             st = apply_inverse(h, h->R_ws, Psi, nrhs, adjoint, 1, s);
             if (st) return st;
@@ -316,6 +387,7 @@ int solve_common(stfem_handle* h, const void* F_dev, void* Psi_dev, int nrhs, vo
         rep->ms_transforms = t[StageTimer::GEMM];
         rep->ms_residual = t[StageTimer::RESID];
         rep->iterations = it;
+        std::memcpy(rep->history, hist, sizeof hist);
         rep->rel_residual = rel;
         rep->kappa_x = h->dec.kappa;
         rep->ms_eig = h->ms_eig;
@@ -363,11 +435,12 @@ extern "C" int shifted_factor_band(const stfem_blocks* b, int l, double* band) {
     clear_error();
     if (!b || !band || l < 0 || l >= b->count) return fail(STFEM_EINVAL, "shifted_factor_band: bad argument");
     const size_t per = (size_t)b->n_x * (b->kd + 1);
+    const size_t stride = (size_t)gpu::band_stride_host(b->n);
     if (b->precision == 64) {
-        HIPCHECK(hipMemcpy(band, (const char*)b->band + (size_t)l * per * 16, per * 16, hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(band, (const char*)b->band + (size_t)l * stride * 16, per * 16, hipMemcpyDeviceToHost));
     } else {
         std::vector<float> tmp(2 * per);
-        HIPCHECK(hipMemcpy(tmp.data(), (const char*)b->band + (size_t)l * per * 8, per * 8, hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(tmp.data(), (const char*)b->band + (size_t)l * stride * 8, per * 8, hipMemcpyDeviceToHost));
         for (size_t i = 0; i < 2 * per; ++i) band[i] = tmp[i];
     }
     return STFEM_OK;
@@ -505,6 +578,11 @@ extern "C" void fdm_destroy(stfem_handle* h) {
     for (double* p : {h->X_dev, h->W_dev, h->tM_dev, h->tB_dev, h->G_ws, h->R_ws, h->partial, h->norms_dev})
         if (p) (void)hipFree(p);
     delete h;
+}
+
+extern "C" void stfem_release_cache(void) {
+    std::lock_guard<std::mutex> lk(g_cache_mutex);
+    release_cache_locked();
 }
 
 // ============================================================ spatial apply

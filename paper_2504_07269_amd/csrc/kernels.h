@@ -17,8 +17,12 @@ struct Stencil {
     int m;      // grid width n-1; n_x = m*m, kd = n = m+1
 };
 
-// Band storage of one block: band[j*(kd+1) + d] = S[j+d][j], d = 0..kd.
+// Band storage of one block: band[j*(kd+1) + d] = S[j+d][j], d = 0..kd;
+// blocks are band_stride() complex values apart.
 // S_l = lambda_l M_x + A_x for l in [0, count); lambda: complex128[count].
+inline long long band_stride_host(int n) {
+    return (((long long)(n - 1) * (n - 1) * (n + 1)) + 63) / 64 * 64;
+}
 hipError_t band_fill(int precision, void* band, const double* lambda, int count, const Stencil& st,
                      hipStream_t s);
 

@@ -58,8 +58,19 @@ __device__ __forceinline__ cpx<R> shfl_xor(cpx<R> v, int mask) {
     return {__shfl_xor(v.x, mask, 64), __shfl_xor(v.y, mask, 64)};
 }
 
-__device__ __forceinline__ long long band_elems(const Stencil& st) {
-    return (long long)st.m * st.m * (st.n + 1);
+// Complex values between consecutive blocks of band storage: n_x (kd + 1)
+// rounded up to a multiple of 64, so that every block starts 512-byte aligned.
+__host__ __device__ __forceinline__ long long band_stride(const Stencil& st) {
+    return (((long long)st.m * st.m * (st.n + 1)) + 63) / 64 * 64;
+}
+
+// Workgroup barrier that orders LDS only.  __syncthreads() also waits for
+// every outstanding global load and store of the thread, which would drain
+// the prefetches issued ahead of their use; this one leaves them in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // ------------------------------------------------------------------ band fill
@@ -69,8 +80,8 @@ __global__ __launch_bounds__(256) void k_band_fill(cpx<R>* __restrict__ band, co
     const int l = blockIdx.y;
     const double lr = lam[2 * l], li = lam[2 * l + 1];
     const int m = st.m, ld = st.n + 1;
-    const long long per = band_elems(st);
-    cpx<R>* B = band + (size_t)l * per;
+    const long long per = (long long)st.m * st.m * (st.n + 1);
+    cpx<R>* B = band + (size_t)l * band_stride(st);
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < per;
          e += (long long)gridDim.x * blockDim.x) {
         const int j = (int)(e / ld), d = (int)(e - (long long)j * ld);
@@ -90,85 +101,333 @@ __global__ __launch_bounds__(256) void k_band_fill(cpx<R>* __restrict__ band, co
     }
 }
 
+__device__ __forceinline__ float rdlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double rdlane(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+template <class R>
+__device__ __forceinline__ cpx<R> rdlane(cpx<R> v, int l) {
+    return {rdlane(v.x, l), rdlane(v.y, l)};
+}
+
+// 16-byte unit of the factor stream: two FP32 complex values or one FP64.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <class R>
+struct Unit;
+template <>
+struct Unit<float> {
+    typedef f32x4 T;
+    static constexpr int CPU = 2;   // complex values per unit
+};
+template <>
+struct Unit<double> {
+    typedef f64x2 T;
+    static constexpr int CPU = 1;
+};
 // ---------------------------------------------------------------------- LDL^T
-// One workgroup factors one band.  Panel of NB columns and its kd+NB rows in
-// LDS (column-major P[c*LP + r], r relative to the panel start k); the panel
-// is factored column by column, written back, and the trailing kd x kd lower
-// triangle is updated in place in global memory:
-//   A[i][j] -= sum_c L[i][c] D_c L[j][c].
+// Matrix-core shapes.  A complex product C += P Q is computed as the real
+// product C' += A' B': every complex row of C is a real row pair (Re, Im) of
+// C', every complex k a real pair of A' columns / B' rows, A' holds the blocks
+// [[Pr, -Pi], [Pi, Pr]] and B' the pairs [Qr; Qi]:
+//   C'(Re row) = sum_k Pr Qr - Pi Qi,   C'(Im row) = sum_k Pi Qr + Pr Qi.
+// FP32: v_mfma_f32_32x32x2f32 = 16 complex rows x 32 complex cols x 1 complex k.
+// FP64: v_mfma_f64_16x16x4f64 =  8 complex rows x 16 complex cols x 2 complex k.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <class R>
+struct Mma;
+template <>
+struct Mma<float> {
+    // C' rows alternate: row 2i = Re(row i), row 2i+1 = Im(row i).
+    // Operand and result lane layout of v_mfma_f32_32x32x2f32 (wave64):
+    // A'[i'][k'] from lane i' + 32 k', B'[k'][j] from lane j + 32 k',
+    // result register r of lane l = C'[8 (r/4) + 4 (l/32) + r%4][l%32].
+    static constexpr int ROWS = 16, COLS = 32, KC = 1, NACC = 16, NENT = 8;
+    typedef f32x16 acc_t;
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+    }
+    // A' element held by `lane`: complex row, real/imag row, complex k, real/imag column
+    static __device__ __forceinline__ int a_row(int lane) { return (lane & 31) >> 1; }
+    static __device__ __forceinline__ int a_im(int lane) { return lane & 1; }
+    static __device__ __forceinline__ int a_k(int) { return 0; }
+    static __device__ __forceinline__ int a_b(int lane) { return lane >> 5; }
+    // B' element: complex column, complex k, real/imag
+    static __device__ __forceinline__ int b_col(int lane) { return lane & 31; }
+    static __device__ __forceinline__ int b_k(int) { return 0; }
+    static __device__ __forceinline__ int b_b(int lane) { return lane >> 5; }
+    // complex result entry e (0..NENT-1) of `lane`: row, and the registers of its parts
+    static __device__ __forceinline__ int e_row(int lane, int e) { return 4 * (e >> 1) + 2 * (lane >> 5) + (e & 1); }
+    static __device__ __forceinline__ int e_re(int e) { return 2 * e; }
+    static __device__ __forceinline__ int e_im(int e) { return 2 * e + 1; }
+    static __device__ __forceinline__ int c_col(int lane) { return lane & 31; }
+};
+template <>
+struct Mma<double> {
+    // C' rows 0-7 = Re(rows 0-7), rows 8-15 = Im(rows 0-7).
+    // v_mfma_f64_16x16x4f64 (wave64): A'[i'][k'] from lane i' + 16 k',
+    // B'[k'][j] from lane j + 16 k', result register r of lane l =
+    // C'[4 r + l/16][l%16].
+    static constexpr int ROWS = 8, COLS = 16, KC = 2, NACC = 4, NENT = 2;
+    typedef f64x4 acc_t;
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int a_row(int lane) { return lane & 7; }
+    static __device__ __forceinline__ int a_im(int lane) { return (lane >> 3) & 1; }
+    static __device__ __forceinline__ int a_k(int lane) { return lane >> 5; }
+    static __device__ __forceinline__ int a_b(int lane) { return (lane >> 4) & 1; }
+    static __device__ __forceinline__ int b_col(int lane) { return lane & 15; }
+    static __device__ __forceinline__ int b_k(int lane) { return lane >> 5; }
+    static __device__ __forceinline__ int b_b(int lane) { return (lane >> 4) & 1; }
+    // registers e and e+2 hold Re and Im of complex row 4 e + l/16 (l/16 in 0..3)
+    static __device__ __forceinline__ int e_row(int lane, int e) { return 4 * e + (lane >> 4); }
+    static __device__ __forceinline__ int e_re(int e) { return e; }
+    static __device__ __forceinline__ int e_im(int e) { return e + 2; }
+    static __device__ __forceinline__ int c_col(int lane) { return lane & 15; }
+};
+
+// Wave-level ordering of LDS accesses (a wave's LDS operations complete in
+// issue order once the compiler keeps that order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup", "local");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One workgroup (4 waves) factors one band as L D L^T, right-looking, NB
+// columns per step.  The NB columns of a step are one contiguous chunk of
+// band storage; they are copied to LDS as they are (Pb[c*ld + d] = entry
+// (k+c+d, k+c)) with 16-byte transfers, and per step:
+//  1. wave 0 factors the NB x NB diagonal block in registers (lane r holds
+//     row r, column multipliers are broadcast between lanes);
+//  2. every thread solves one row below the block, left-looking in
+//     registers: L[r][c] D_c = A[r][c] - sum_{c'<c} L[r][c'] D_c' L[c][c'];
+//  3. the chunk goes back to global memory (final L and D);
+//  4. the trailing kd x kd lower triangle, in global memory, gets
+//     A -= (L D) L^T on the matrix cores, in square tiles of Mma::COLS complex
+//     rows and columns (two matrix-core row blocks per tile); a wave keeps one
+//     tile row's A' operands in registers and sweeps that row's tiles, loading
+//     the next tile while the current one is in the matrix pipe; tile rows are
+//     paired (I, T-1-I) across waves for balance.
 template <class R, int NB>
-__global__ __launch_bounds__(256) void k_ldlt(cpx<R>* __restrict__ band, Stencil st, int* __restrict__ info) {
+__global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Stencil st, int* __restrict__ info) {
+    typedef Mma<R> MM;
+    typedef typename Unit<R>::T UT;
+    constexpr int CPU = Unit<R>::CPU;
+    constexpr int TS = MM::COLS;          // tile size (complex rows = cols)
+    constexpr int RB = TS / MM::ROWS;     // matrix-core row blocks per tile (2)
+    constexpr int KS = NB / MM::KC;       // matrix-core k steps per tile
+    constexpr int QB = 16;                // 16-byte transfers in flight per thread
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cpx<R>* P = reinterpret_cast<cpx<R>*>(smem_raw);
-    const int m = st.m, kd = st.n, n_x = m * m, ld = kd + 1, LP = NB + kd;
+    const int m = st.m, kd = st.n, n_x = m * m, ld = kd + 1;
+    cpx<R>* Pb = reinterpret_cast<cpx<R>*>(smem_raw);                 // NB*ld, rounded to units
+    cpx<R>* Dinv = Pb + (NB * ld + CPU - 1) / CPU * CPU;             // NB
+    R* Bsw = reinterpret_cast<R*>(Dinv + NB);                         // ceil(kd/TS) * 64 * KS
     const int l = blockIdx.x;
-    cpx<R>* A = band + (size_t)l * band_elems(st);
-    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
+    cpx<R>* A = band + (size_t)l * band_stride(st);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = 4;
+    const cpx<R> zero = {R(0), R(0)};
     int bad = 0;
+    // entry (row r, column c) of the panel, relative to the step start
+    auto PV = [&](int c, int r) -> cpx<R> {
+        const int d = r - c;
+        return (d >= 0 && d <= kd) ? Pb[c * ld + d] : zero;
+    };
     for (int k = 0; k < n_x; k += NB) {
         const int nb = min(NB, n_x - k);
         const int mrows = min(nb + kd, n_x - k);
-        for (int e = tid; e < nb * mrows; e += nth) {
-            const int c = e / mrows, r = e - c * mrows;
-            cpx<R> v = {R(0), R(0)};
-            if (r >= c && r - c <= kd) v = A[(size_t)(k + c) * ld + (r - c)];
-            P[c * LP + r] = v;
-        }
-        __syncthreads();
-        for (int c = 0; c < nb; ++c) {
-            bool ok;
-            const cpx<R> inv = cinv_or_zero(P[c * LP + c], ok);
-            if (!ok && bad == 0) bad = k + c + 1;
-            const int nr = mrows - (c + 1), ncol = nb - c - 1;
-            for (int e = tid; e < ncol * nr; e += nth) {
-                const int c2 = c + 1 + e / nr, r = c + 1 + e % nr;
-                if (r < c2) continue;
-                const cpx<R> lc2 = cmul(P[c * LP + c2], inv);
-                P[c2 * LP + r] = csub(P[c2 * LP + r], cmul(P[c * LP + r], lc2));
+        const int units = (nb * ld + CPU - 1) / CPU;
+        // ---- panel chunk to LDS
+        {
+            const UT* src = reinterpret_cast<const UT*>(A + (size_t)k * ld);
+            UT* dst = reinterpret_cast<UT*>(Pb);
+            for (int base = 0; base < units; base += QB * 256) {
+                UT q[QB];
+#pragma unroll
+                for (int j = 0; j < QB; ++j) {
+                    const int e = base + tid + 256 * j;
+                    if (e < units) q[j] = src[e];
+                }
+#pragma unroll
+                for (int j = 0; j < QB; ++j) {
+                    const int e = base + tid + 256 * j;
+                    if (e < units) dst[e] = q[j];
+                }
             }
-            __syncthreads();
-            for (int r = c + 1 + tid; r < mrows; r += nth) P[c * LP + r] = cmul(P[c * LP + r], inv);
-            __syncthreads();
         }
-        for (int e = tid; e < nb * ld; e += nth) {
-            const int c = e / ld, d = e - c * ld;
-            if (c + d < mrows) A[(size_t)(k + c) * ld + d] = P[c * LP + c + d];
+        lds_barrier();
+        // ---- 1. diagonal block (wave 0, lane r = row r)
+        if (wave == 0) {
+            const int r = lane;
+            cpx<R> y[NB];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) y[c] = (r < nb && c <= r && c < nb) ? PV(c, r) : zero;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                if (c < nb) {
+                    bool ok;
+                    const cpx<R> d = rdlane(y[c], c);
+                    const cpx<R> inv = cinv_or_zero(d, ok);
+                    if (!ok && bad == 0) bad = k + c + 1;
+                    const cpx<R> lr = cmul(y[c], inv);          // L[r][c] for r > c
+                    const cpx<R> ld_r = cmul(lr, d);            // L[r][c] D_c
+#pragma unroll
+                    for (int c2 = c + 1; c2 < NB; ++c2) {
+                        const cpx<R> lc2 = rdlane(lr, c2);      // L[c2][c]
+                        y[c2] = csub(y[c2], cmul(ld_r, lc2));
+                    }
+                    if (r > c) y[c] = lr;
+                    if (r == c) Dinv[c] = inv;
+                }
+            }
+            if (r < nb) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c)
+                    if (c <= r && r - c <= kd) Pb[c * ld + (r - c)] = y[c];
+            }
         }
-        // trailing update: columns jl in [nb, mrows), rows il in [jl, mrows)
-        // (relative to k), in items of 4 columns x 64 rows, round-robin over waves
-        const int ncols = mrows - nb;
-        const int ngroups = (ncols + 3) >> 2;
-        int item = 0;
-        for (int g = 0; g < ngroups; ++g) {
-            const int jl0 = nb + 4 * g;
-            const int nchunk = (mrows - jl0 + 63) >> 6;
-            for (int q = 0; q < nchunk; ++q, ++item) {
-                if (item % nwave != wave) continue;
-                const int il = jl0 + 64 * q + lane;
-                if (il >= mrows) continue;
-                cpx<R> a[4];
-                size_t idx[4];
+        lds_barrier();
+        // ---- 2. rows below the diagonal block, 8 columns at a time; the
+        //      finished columns hold y = L D until the final scaling by D^{-1}
+        for (int r = nb + tid; r < mrows; r += 256) {
+            for (int c0 = 0; c0 < nb; c0 += 8) {
+                cpx<R> y[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int jl = jl0 + u;
-                    idx[u] = (size_t)(k + jl) * ld + (il - jl);
-                    a[u] = (jl < mrows && il >= jl) ? A[idx[u]] : cpx<R>{R(0), R(0)};
-                }
-                cpx<R> acc[4] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
-                const int j1 = min(jl0 + 1, mrows - 1), j2 = min(jl0 + 2, mrows - 1), j3 = min(jl0 + 3, mrows - 1);
-                for (int c = 0; c < nb; ++c) {
-                    const cpx<R>* Pc = P + c * LP;
-                    const cpx<R> t = cmul(Pc[c], Pc[il]);     // D_c L[i][c]
-                    acc[0] = cfma(t, Pc[jl0], acc[0]);
-                    acc[1] = cfma(t, Pc[j1], acc[1]);
-                    acc[2] = cfma(t, Pc[j2], acc[2]);
-                    acc[3] = cfma(t, Pc[j3], acc[3]);
+                for (int u = 0; u < 8; ++u) y[u] = (c0 + u < nb) ? PV(c0 + u, r) : zero;
+#pragma unroll 4
+                for (int c2 = 0; c2 < c0; ++c2) {            // finished columns
+                    const cpx<R> yc = PV(c2, r);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) y[u] = csub(y[u], cmul(yc, Pb[c2 * ld + (c0 + u - c2)]));
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int jl = jl0 + u;
-                    if (jl < mrows && il >= jl) A[idx[u]] = csub(a[u], acc[u]);
+                for (int u = 1; u < 8; ++u) {                // within the block
+#pragma unroll
+                    for (int v = 0; v < u; ++v) y[u] = csub(y[u], cmul(y[v], Pb[(c0 + v) * ld + (u - v)]));
                 }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (c0 + u < nb && r - (c0 + u) <= kd) Pb[(c0 + u) * ld + (r - c0 - u)] = y[u];
+            }
+            for (int c = 0; c < nb; ++c)
+                if (r - c <= kd) Pb[c * ld + (r - c)] = cmul(Pb[c * ld + (r - c)], Dinv[c]);
+        }
+        lds_barrier();
+        // ---- 3. panel chunk back to global memory
+        {
+            UT* dst = reinterpret_cast<UT*>(A + (size_t)k * ld);
+            const UT* src = reinterpret_cast<const UT*>(Pb);
+            for (int e = tid; e < units; e += 256) dst[e] = src[e];
+        }
+        // ---- 4. B' operands of every tile column, once for all waves:
+        //      Bsw[(J*64 + lane)*KS + s] is what `lane` feeds the matrix cores
+        //      at k step s for tile column J
+        const int ntr = mrows - nb;               // trailing rows/cols
+        const int TT = (ntr + TS - 1) / TS;       // tile rows
+        for (int e = tid; e < TT * 64 * KS; e += 256) {
+            const int s = e % KS, ln = (e / KS) & 63, J = e / (KS * 64);
+            const int c = s * MM::KC + MM::b_k(ln), cc = TS * J + MM::b_col(ln);
+            const cpx<R> qv = (cc < ntr && c < nb) ? PV(c, nb + cc) : zero;
+            Bsw[e] = MM::b_b(ln) ? qv.y : qv.x;
+        }
+        lds_barrier();
+        // ---- 5. trailing update on the matrix cores
+        const int npairs = (TT + 2 * NW - 1) / (2 * NW);
+        for (int q = 0; q < 2 * npairs; ++q) {
+            const int p = q >> 1;
+            const int I = (q & 1) ? 2 * NW * p + 2 * NW - 1 - wave : 2 * NW * p + wave;
+            if (I >= TT) continue;
+            // A' operands of tile row I: -(L D) in 2x2 real-block form
+            R av[RB][KS];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const int rr = TS * I + MM::ROWS * rb + MM::a_row(lane);
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    const int c = s * MM::KC + MM::a_k(lane);
+                    cpx<R> pv = zero;
+                    if (rr < ntr && c < nb) pv = cmul(Pb[c * ld], PV(c, nb + rr));
+                    const int im = MM::a_im(lane), b = MM::a_b(lane);
+                    av[rb][s] = (im == b) ? -pv.x : (im ? -pv.y : pv.y);
+                }
+            }
+            const bool rows_full = TS * (I + 1) <= ntr;
+            // row of accumulator entry e of row block rb, relative to the tile
+            auto trow = [&](int rb, int e) { return MM::ROWS * rb + MM::e_row(lane, e); };
+            // C tile (I, J) into registers; zero outside the lower triangle
+            auto load_c = [&](int J, typename MM::acc_t (&acc)[RB]) {
+                const int cc = TS * J + MM::c_col(lane);
+                cpx<R>* col = A + (size_t)(k + nb + cc) * ld - cc + TS * I;
+                if (J < I && rows_full) {
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int e = 0; e < MM::NENT; ++e) {
+                            const cpx<R> cv = col[trow(rb, e)];
+                            acc[rb][MM::e_re(e)] = cv.x;
+                            acc[rb][MM::e_im(e)] = cv.y;
+                        }
+                } else {
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int e = 0; e < MM::NENT; ++e) {
+                            const int rr = TS * I + trow(rb, e);
+                            cpx<R> cv = zero;
+                            if (J <= I && rr < ntr && cc < ntr && rr >= cc) cv = col[trow(rb, e)];
+                            acc[rb][MM::e_re(e)] = cv.x;
+                            acc[rb][MM::e_im(e)] = cv.y;
+                        }
+                }
+            };
+            auto store_c = [&](int J, const typename MM::acc_t (&acc)[RB]) {
+                const int cc = TS * J + MM::c_col(lane);
+                cpx<R>* col = A + (size_t)(k + nb + cc) * ld - cc + TS * I;
+                if (J < I && rows_full) {
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int e = 0; e < MM::NENT; ++e)
+                            col[trow(rb, e)] = cpx<R>{acc[rb][MM::e_re(e)], acc[rb][MM::e_im(e)]};
+                } else {
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int e = 0; e < MM::NENT; ++e) {
+                            const int rr = TS * I + trow(rb, e);
+                            if (rr < ntr && cc < ntr && rr >= cc)
+                                col[trow(rb, e)] = cpx<R>{acc[rb][MM::e_re(e)], acc[rb][MM::e_im(e)]};
+                        }
+                }
+            };
+            typename MM::acc_t acc[RB], accn[RB];
+            load_c(0, acc);
+            for (int J = 0; J <= I; ++J) {
+                load_c(J + 1, accn);                 // next tile, in flight during the MFMAs
+                R bv[KS];
+                const typename Unit<R>::T* bsrc =
+                    reinterpret_cast<const typename Unit<R>::T*>(Bsw + (size_t)(J * 64 + lane) * KS);
+                constexpr int RPU = 16 / sizeof(R);  // reals per 16-byte unit
+#pragma unroll
+                for (int s = 0; s < KS / RPU; ++s) {
+                    const typename Unit<R>::T v = bsrc[s];
+#pragma unroll
+                    for (int t = 0; t < RPU; ++t) bv[RPU * s + t] = v[t];
+                }
+#pragma unroll
+                for (int s = 0; s < KS; ++s)
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) acc[rb] = MM::mma(av[rb][s], bv[s], acc[rb]);
+                store_c(J, acc);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) acc[rb] = accn[rb];
             }
         }
         __syncthreads();
@@ -177,187 +436,245 @@ __global__ __launch_bounds__(256) void k_ldlt(cpx<R>* __restrict__ band, Stencil
 }
 
 // ---------------------------------------------------------------------- sweeps
-// One workgroup solves S_l x = g for up to 4 right-hand sides.  The rows that
-// a panel of NB columns touches (kd+NB of them) live in an LDS ring of
-// Sz = kd + 2 NB slots per rhs.  Forward, per panel: wave 0 solves the unit
-// triangle of the diagonal NB x NB block with lane shuffles, then all threads
-// apply the panel to the kd rows below (threads over rows, coalesced reads of
-// L's columns).  Backward (L^T x = z), per panel from the bottom: all waves
-// form the dot products of the panel columns with the finished x below
-// (lanes over rows, wave reductions), then wave 0 solves the transposed
-// diagonal triangle.  KS = ceil(kd / 256).
-template <class R, int NB, int KS, bool CONJ>
-__global__ __launch_bounds__(256) void k_sweep(const cpx<R>* __restrict__ band, Stencil st, const double* G,
-                                               double* U, int nr, long long rstride) {
+constexpr int SWEEP_QL = 9;        // 16-byte units per producer thread and panel
+
+// One workgroup of 8 waves solves S_l x = g for NR right-hand sides:
+// L y = g, z = D^{-1} y, L^T x = z.  The sweeps walk the factor panel by
+// panel (NB columns); a panel, NB columns of band storage, is one contiguous
+// chunk of memory.  Waves 4-7 are producers: they stream panels from HBM into
+// a ring of three LDS slots, two panels ahead of their use, so their waits on
+// memory never stall the arithmetic.  Waves 0-3 are consumers; the rows a
+// panel touches (kd + NB) live in an LDS ring of Sz slots per rhs (Sz a power
+// of two >= kd + 2 NB).
+//  forward  consumer wave 0 solves the unit triangle of the diagonal block
+//           (register broadcasts between lanes), then every consumer thread
+//           updates one of the kd rows below;
+//  backward every consumer wave forms dot products of its panel columns with
+//           the finished x below (lanes over rows, wave reductions), then
+//           wave 0 solves the transposed diagonal triangle.
+// Each panel step has three workgroup barriers, all of them LDS-only: no wave
+// waits at a barrier for its own global loads.  A producer stores the panel
+// it loaded one step earlier and then issues the loads of the next one.
+template <class R, int NB, int NR, int KQ, bool CONJ>
+__global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ band, Stencil st, const double* G,
+                                                  double* U, long long rstride, int Sz) {
+    typedef typename Unit<R>::T UT;
+    constexpr int CPU = Unit<R>::CPU;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int m = st.m, kd = st.n, n_x = m * m, ld = kd + 1;
-    const int Sz = kd + 2 * NB;
-    cpx<R>* Y = reinterpret_cast<cpx<R>*>(smem_raw);   // Y[rh*Sz + slot]
-    cpx<R>* S = Y + 4 * Sz;                           // S[rh*NB + c]
+    const int msk = Sz - 1;
+    const int slot_units = (NB * ld + CPU - 1) / CPU;
+    UT* ring = reinterpret_cast<UT*>(smem_raw);                       // 3 * slot_units
+    cpx<R>* Y = reinterpret_cast<cpx<R>*>(ring + 3 * slot_units);      // Y[rh*Sz + slot]
+    cpx<R>* S = Y + NR * Sz;                                          // S[rh*NB + c]
     const int l = blockIdx.x;
-    const cpx<R>* L = band + (size_t)l * band_elems(st);
+    const cpx<R>* Lb = band + (size_t)l * band_stride(st);
     const double2* g = reinterpret_cast<const double2*>(G) + (size_t)l * n_x;
     double2* u = reinterpret_cast<double2*>(U) + (size_t)l * n_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool producer = wave >= 4;
+    const int ptid = tid - 256;           // producer thread index
+    const int npanel = (n_x + NB - 1) / NB;
+    const cpx<R> cz = {R(0), R(0)};
 
-    auto ldL = [&](int row, int col) -> cpx<R> {   // L[row][col] (or D at row == col), 0 <= row-col <= kd
-        cpx<R> v = L[(size_t)col * ld + (row - col)];
+    // ---- producers: panel p is loaded into registers one step before it is
+    // stored into its ring slot, so each load has a whole panel step to land
+    UT q[SWEEP_QL];
+    auto pload = [&](int p) {
+        p = min(max(p, 0), npanel - 1);
+        const int k = p * NB, nb = min(NB, n_x - k);
+        const int units = (nb * ld + CPU - 1) / CPU;
+        const UT* src = reinterpret_cast<const UT*>(Lb + (size_t)k * ld);
+#pragma unroll
+        for (int j = 0; j < SWEEP_QL; ++j) q[j] = src[min(ptid + 256 * j, units - 1)];
+    };
+    auto pstore = [&](int p, int slot) {
+        const int k = p * NB, nb = min(NB, n_x - k);
+        const int units = (nb * ld + CPU - 1) / CPU;
+        UT* dst = ring + slot * slot_units;
+#pragma unroll
+        for (int j = 0; j < SWEEP_QL; ++j) {
+            const int e = ptid + 256 * j;
+            if (e < units) dst[e] = q[j];
+        }
+    };
+    // ---- consumers: entry (k+r, k+c) of the panel in `slot`, 0 <= r - c <= kd
+    auto PV = [&](int slot, int c, int r) -> cpx<R> {
+        cpx<R> v = reinterpret_cast<const cpx<R>*>(ring + slot * slot_units)[c * ld + (r - c)];
         if (CONJ) v.y = -v.y;
         return v;
     };
 
-    // initial window: rows [0, min(NB + kd, n_x))
-    {
+    // ===================================================== forward sweep
+    if (producer) {
+        pload(0);
+        pstore(0, 0);
+        pload(1);
+        if (npanel > 1) pstore(1, 1);
+        pload(2);
+    } else {
         const int rows0 = min(NB + kd, n_x);
-        for (int e = tid; e < nr * rows0; e += blockDim.x) {
+        for (int e = tid; e < NR * rows0; e += 256) {
             const int rh = e / rows0, i = e - rh * rows0;
             const double2 v = g[(size_t)rh * rstride + i];
-            Y[rh * Sz + i % Sz] = {(R)v.x, (R)v.y};
+            Y[rh * Sz + (i & msk)] = {(R)v.x, (R)v.y};
         }
     }
-    __syncthreads();
-
-    // ------------------------------------------------------------- forward
-    for (int k = 0; k < n_x; k += NB) {
-        const int nb = min(NB, n_x - k);
-        // prefetch this thread's panel rows for the update below
-        cpx<R> Lr[KS][NB];
+    lds_barrier();
+    for (int p = 0; p < npanel; ++p) {
+        const int slot = p % 3;
+        const int k = p * NB, nb = min(NB, n_x - k);
+        const int rh_in = min(tid / NB, NR - 1), i_in = k + NB + kd + (tid % NB);
+        const bool has_in = !producer && tid < NB * NR && i_in < n_x;
+        double2 gin = make_double2(0.0, 0.0);
+        // phase 1: triangle of the diagonal block
+        if (!producer) {
+            gin = g[(size_t)rh_in * rstride + min(i_in, n_x - 1)];
+            if (wave == 0) {
+                const int r = lane;
+                const int ys = (k + min(r, nb - 1)) & msk;
+                cpx<R> lrow[NB];                              // L[k+r][k+c], c < r
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const int i = k + nb + tid + 256 * s;
+                for (int c = 0; c < NB - 1; ++c) lrow[c] = (r > c && r < nb && r - c <= kd) ? PV(slot, c, r) : cz;
+                const cpx<R> dv = (r < nb) ? PV(slot, r, r) : cpx<R>{R(1), R(0)};
+                cpx<R> y[NR];
 #pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                const bool in = (c < nb) && (i < n_x) && (i - (k + c) <= kd) && (tid + 256 * s < kd);
-                Lr[s][c] = in ? ldL(i, k + c) : cpx<R>{R(0), R(0)};
-            }
-        }
-        if (wave == 0) {
-            const int r = lane;
-            cpx<R> y[4];
-            cpx<R> Lrow[NB];
+                for (int rh = 0; rh < NR; ++rh) y[rh] = Y[rh * Sz + ys];
 #pragma unroll
-            for (int c = 0; c < NB; ++c)
-                Lrow[c] = (r < nb && c < r && r - c <= kd) ? ldL(k + r, k + c) : cpx<R>{R(0), R(0)};
-            const int slot = (k + min(r, nb - 1)) % Sz;
+                for (int c = 0; c < NB - 1; ++c) {
 #pragma unroll
-            for (int rh = 0; rh < 4; ++rh) y[rh] = (rh < nr) ? Y[rh * Sz + slot] : cpx<R>{R(0), R(0)};
-#pragma unroll
-            for (int c = 0; c < NB - 1; ++c) {
-#pragma unroll
-                for (int rh = 0; rh < 4; ++rh) {
-                    const cpx<R> yc = shfl(y[rh], c);
-                    if (r > c) y[rh] = csub(y[rh], cmul(Lrow[c], yc));   // Lrow[c] = 0 beyond nb
+                    for (int rh = 0; rh < NR; ++rh) y[rh] = csub(y[rh], cmul(lrow[c], rdlane(y[rh], c)));
                 }
-            }
-            if (r < nb) {
-                bool ok;
-                const cpx<R> dinv = cinv_or_zero(ldL(k + r, k + r), ok);
+                if (r < nb) {
+                    bool ok;
+                    const cpx<R> dinv = cinv_or_zero(dv, ok);
 #pragma unroll
-                for (int rh = 0; rh < 4; ++rh) {
-                    if (rh < nr) {
-                        Y[rh * Sz + slot] = y[rh];
+                    for (int rh = 0; rh < NR; ++rh) {
+                        Y[rh * Sz + ys] = y[rh];
                         const cpx<R> z = cmul(y[rh], dinv);
                         u[(size_t)rh * rstride + k + r] = make_double2((double)z.x, (double)z.y);
                     }
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
+        // phase 2: the kd rows below the panel
+        if (!producer) {
+            for (int t = tid; t < kd; t += 256) {
+                const int i = k + nb + t;
+                if (i < n_x) {
+                    cpx<R> acc[NR];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const int t = tid + 256 * s, i = k + nb + t;
-            if (t < kd && i < n_x) {
+                    for (int rh = 0; rh < NR; ++rh) acc[rh] = cz;
+                    const int c0 = nb + t - kd;               // columns whose band reaches row i
 #pragma unroll
-                for (int rh = 0; rh < 4; ++rh) {
-                    if (rh < nr) {
-                        cpx<R> acc = {R(0), R(0)};
+                    for (int c = 0; c < NB; ++c) {
+                        if (c >= c0 && c < nb) {
+                            const cpx<R> lv = PV(slot, c, nb + t);
 #pragma unroll
-                        for (int c = 0; c < NB; ++c)   // Lr[s][c] = 0 for c >= nb
-                            acc = cfma(Lr[s][c], Y[rh * Sz + (k + c) % Sz], acc);
-                        cpx<R>& yi = Y[rh * Sz + i % Sz];
-                        yi = csub(yi, acc);
+                            for (int rh = 0; rh < NR; ++rh) acc[rh] = cfma(lv, Y[rh * Sz + ((k + c) & msk)], acc[rh]);
+                        }
+                    }
+#pragma unroll
+                    for (int rh = 0; rh < NR; ++rh) {
+                        cpx<R>& yi = Y[rh * Sz + (i & msk)];
+                        yi = csub(yi, acc[rh]);
                     }
                 }
             }
         }
-        // rows entering the window for the next panel
-        if (tid < NB * nr) {
-            const int rh = tid / NB, a = tid - rh * NB;
-            const int i = k + NB + kd + a;
-            if (i < n_x) {
-                const double2 v = g[(size_t)rh * rstride + i];
-                Y[rh * Sz + i % Sz] = {(R)v.x, (R)v.y};
-            }
+        lds_barrier();
+        // phase 3: producers fill the slot of panel p+2; rows entering the window
+        if (producer) {
+            if (p + 2 < npanel) pstore(p + 2, (p + 2) % 3);
+            pload(p + 3);
+        } else if (has_in) {
+            Y[rh_in * Sz + (i_in & msk)] = {(R)gin.x, (R)gin.y};
         }
-        __syncthreads();
+        lds_barrier();
     }
 
-    // ------------------------------------------------------------ backward
-    const int kb = ((n_x - 1) / NB) * NB;
-    for (int k = kb; k >= 0; k -= NB) {
-        const int nb = min(NB, n_x - k);
-        // dot products of panel columns with the finished x below the panel
-        for (int c = wave; c < nb; c += 4) {
-            cpx<R> part[4] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
-            const int col = k + c;
-            const int ilast = min(col + kd, n_x - 1);
+    // ==================================================== backward sweep
+    // panel p = npanel-1-b is consumed at backward step b from slot b % 3
+    if (producer) {
+        pload(npanel - 1);
+        pstore(npanel - 1, 0);
+        pload(npanel - 2);
+        if (npanel > 1) pstore(npanel - 2, 1);
+        pload(npanel - 3);
+    }
+    lds_barrier();
+    for (int b = 0; b < npanel; ++b) {
+        const int slot = b % 3;
+        const int p = npanel - 1 - b;
+        const int k = p * NB, nb = min(NB, n_x - k);
+        // phase 1: dot products of the panel columns with the finished x below
+        cpx<R> zc[NR];
+        if (!producer) {
+            if (wave == 0) {
 #pragma unroll
-            for (int p = 0; p < 4 * KS; ++p) {
-                const int i = k + nb + lane + 64 * p;
-                if (i <= ilast) {
-                    const cpx<R> lv = ldL(i, col);
-#pragma unroll
-                    for (int rh = 0; rh < 4; ++rh)
-                        if (rh < nr) part[rh] = cfma(lv, Y[rh * Sz + i % Sz], part[rh]);
+                for (int rh = 0; rh < NR; ++rh) {
+                    const double2 z = u[(size_t)rh * rstride + min(k + lane, n_x - 1)];
+                    zc[rh] = {(R)z.x, (R)z.y};
                 }
             }
+            for (int c = wave; c < nb; c += 4) {
+                const int ilast = min(k + c + kd, n_x - 1);
+                cpx<R> part[NR];
 #pragma unroll
-            for (int rh = 0; rh < 4; ++rh) {
-                cpx<R> v = part[rh];
+                for (int rh = 0; rh < NR; ++rh) part[rh] = cz;
 #pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) {
-                    const cpx<R> o = shfl_xor(v, off);
-                    v.x += o.x;
-                    v.y += o.y;
+                for (int pq = 0; pq < 4 * KQ; ++pq) {
+                    const int i = k + nb + lane + 64 * pq;
+                    if (i <= ilast) {
+                        const cpx<R> lv = PV(slot, c, i - k);
+#pragma unroll
+                        for (int rh = 0; rh < NR; ++rh) part[rh] = cfma(lv, Y[rh * Sz + (i & msk)], part[rh]);
+                    }
                 }
-                if (lane == 0 && rh < nr) S[rh * NB + c] = v;
+#pragma unroll
+                for (int rh = 0; rh < NR; ++rh) {
+                    cpx<R> v = part[rh];
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1) {
+                        const cpx<R> o = shfl_xor(v, off);
+                        v.x += o.x;
+                        v.y += o.y;
+                    }
+                    if (lane == 0) S[rh * NB + c] = v;
+                }
             }
         }
-        __syncthreads();
-        if (wave == 0) {
+        lds_barrier();
+        // phase 2: transposed triangle of the diagonal block
+        if (!producer && wave == 0) {
             const int r = lane;
-            cpx<R> v[4];
-            cpx<R> Lt[NB];
+            cpx<R> lcol[NB];                                  // L[k+c][k+r], c > r
 #pragma unroll
-            for (int c = 0; c < NB; ++c)
-                Lt[c] = (r < nb && c > r && c < nb && c - r <= kd) ? ldL(k + c, k + r) : cpx<R>{R(0), R(0)};
+            for (int c = 1; c < NB; ++c) lcol[c] = (r < c && c < nb && c - r <= kd) ? PV(slot, r, c) : cz;
+            cpx<R> v[NR];
 #pragma unroll
-            for (int rh = 0; rh < 4; ++rh) {
-                v[rh] = {R(0), R(0)};
-                if (rh < nr && r < nb) {
-                    const double2 z = u[(size_t)rh * rstride + k + r];
-                    v[rh] = csub(cpx<R>{(R)z.x, (R)z.y}, S[rh * NB + r]);
-                }
-            }
+            for (int rh = 0; rh < NR; ++rh) v[rh] = (r < nb) ? csub(zc[rh], S[rh * NB + r]) : cz;
 #pragma unroll
             for (int c = NB - 1; c >= 1; --c) {
 #pragma unroll
-                for (int rh = 0; rh < 4; ++rh) {
-                    const cpx<R> xc = shfl(v[rh], c);
-                    if (r < c) v[rh] = csub(v[rh], cmul(Lt[c], xc));   // Lt[c] = 0 for c >= nb
-                }
+                for (int rh = 0; rh < NR; ++rh) v[rh] = csub(v[rh], cmul(lcol[c], rdlane(v[rh], c)));
             }
             if (r < nb) {
 #pragma unroll
-                for (int rh = 0; rh < 4; ++rh) {
-                    if (rh < nr) {
-                        Y[rh * Sz + (k + r) % Sz] = v[rh];
-                        u[(size_t)rh * rstride + k + r] = make_double2((double)v[rh].x, (double)v[rh].y);
-                    }
+                for (int rh = 0; rh < NR; ++rh) {
+                    Y[rh * Sz + ((k + r) & msk)] = v[rh];
+                    u[(size_t)rh * rstride + k + r] = make_double2((double)v[rh].x, (double)v[rh].y);
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
+        // phase 3: producers fill the slot of backward step b+2
+        if (producer) {
+            if (b + 2 < npanel) pstore(npanel - 3 - b, (b + 2) % 3);
+            pload(npanel - 4 - b);
+        }
+        lds_barrier();
     }
 }
 
@@ -557,17 +874,19 @@ __global__ void k_fill_int(int* p, int count, int value) {
     if (i < count) p[i] = value;
 }
 
-// LDS panel width for the factorisation: the largest of 32, 16, 8 whose panel
-// ((NB + kd) x NB complex values) stays within 150 KiB.
-int ldlt_nb(int kd, size_t elem) {
-    for (int nb : {32, 16, 8})
-        if ((size_t)(nb + kd) * nb * elem <= 150u * 1024u) return nb;
-    return 0;
+// LDS of the factorisation: the panel (NB (kd + 1) complex values), D^{-1}
+// and the swizzled B' operands (ceil(kd / TS) tiles x 64 lanes x NB / KC).
+template <class R, int NB>
+size_t ldlt_lds_bytes(int kd) {
+    constexpr int CPU = Unit<R>::CPU;
+    const size_t panel = (size_t)(NB * (kd + 1) + CPU - 1) / CPU * CPU + NB;
+    const size_t tiles = (size_t)(kd + Mma<R>::COLS - 1) / Mma<R>::COLS;
+    return panel * sizeof(cpx<R>) + tiles * 64 * (NB / Mma<R>::KC) * sizeof(R);
 }
 
 template <class R, int NB>
 hipError_t launch_ldlt(void* band, int count, const Stencil& st, int* info, hipStream_t s) {
-    const size_t lds = (size_t)(NB + st.n) * NB * sizeof(cpx<R>);
+    const size_t lds = ldlt_lds_bytes<R, NB>(st.n);
     auto kern = k_ldlt<R, NB>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -575,40 +894,74 @@ hipError_t launch_ldlt(void* band, int count, const Stencil& st, int* info, hipS
     return hipGetLastError();
 }
 
-template <class R, int NB, int KS>
-hipError_t launch_sweep_ks(const void* band, int count, const Stencil& st, const double* G, double* U, int nrhs,
+template <class R, int NB, int NR, int KQ>
+hipError_t launch_sweep_nr(const void* band, int count, const Stencil& st, const double* G, double* U, int conj,
+                           long long rstride, hipStream_t s) {
+    int Sz = 1;
+    while (Sz < st.n + 2 * NB) Sz <<= 1;
+    constexpr int CPU = Unit<R>::CPU;
+    const size_t slot = (size_t)(NB * (st.n + 1) + CPU - 1) / CPU;   // 16-byte units
+    const size_t lds = 3 * slot * 16 + (NR * Sz + NR * NB) * sizeof(cpx<R>);
+    if ((size_t)NB * (st.n + 1) > (size_t)SWEEP_QL * 256 * CPU) return hipErrorInvalidValue;
+    if (conj) {
+        auto kern = k_sweep<R, NB, NR, KQ, true>;
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(count), dim3(512), lds, s, (const cpx<R>*)band, st, G, U, rstride, Sz);
+    } else {
+        auto kern = k_sweep<R, NB, NR, KQ, false>;
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(count), dim3(512), lds, s, (const cpx<R>*)band, st, G, U, rstride, Sz);
+    }
+    return hipGetLastError();
+}
+
+// Right-hand sides go through the kernel 4, then 2, then 1 at a time.
+template <class R, int NB, int KQ>
+hipError_t launch_sweep_nb(const void* band, int count, const Stencil& st, const double* G, double* U, int nrhs,
                            int conj, hipStream_t s) {
-    const int Sz = st.n + 2 * NB;
-    const size_t lds = (size_t)(4 * Sz + 4 * NB) * sizeof(cpx<R>);
-    const long long rstride = (long long)count * st.m * st.m * 2;   // doubles between rhs
-    for (int r0 = 0; r0 < nrhs; r0 += 4) {
-        const int nr = std::min(4, nrhs - r0);
-        const double* Gr = G + (size_t)r0 * rstride;
-        double* Ur = U + (size_t)r0 * rstride;
-        if (conj) {
-            auto kern = k_sweep<R, NB, KS, true>;
-            hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(kern, dim3(count), dim3(256), lds, s, (const cpx<R>*)band, st, Gr, Ur, nr, rstride / 2);
+    const long long rstride = (long long)count * st.m * st.m;   // complex elements between rhs
+    int r0 = 0;
+    while (r0 < nrhs) {
+        const int left = nrhs - r0;
+        const double* Gr = G + (size_t)r0 * rstride * 2;
+        double* Ur = U + (size_t)r0 * rstride * 2;
+        hipError_t e;
+        if (left >= 4) {
+            e = launch_sweep_nr<R, NB, 4, KQ>(band, count, st, Gr, Ur, conj, rstride, s);
+            r0 += 4;
+        } else if (left >= 2) {
+            e = launch_sweep_nr<R, NB, 2, KQ>(band, count, st, Gr, Ur, conj, rstride, s);
+            r0 += 2;
         } else {
-            auto kern = k_sweep<R, NB, KS, false>;
-            hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(kern, dim3(count), dim3(256), lds, s, (const cpx<R>*)band, st, Gr, Ur, nr, rstride / 2);
+            e = launch_sweep_nr<R, NB, 1, KQ>(band, count, st, Gr, Ur, conj, rstride, s);
+            r0 += 1;
         }
-        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
+// Panel width of the sweeps: the widest of 16, 8, 4 columns whose panel
+// (NB (kd + 1) complex values) fits the SWEEP_QL 16-byte loads per thread.
+template <class R, int KQ>
+hipError_t launch_sweep_kq(const void* band, int count, const Stencil& st, const double* G, double* U, int nrhs,
+                           int conj, hipStream_t s) {
+    const size_t cap = (size_t)SWEEP_QL * 256 * Unit<R>::CPU;
+    const size_t ld = st.n + 1;
+    if (16 * ld <= cap) return launch_sweep_nb<R, 16, KQ>(band, count, st, G, U, nrhs, conj, s);
+    if (8 * ld <= cap) return launch_sweep_nb<R, 8, KQ>(band, count, st, G, U, nrhs, conj, s);
+    if (4 * ld <= cap) return launch_sweep_nb<R, 4, KQ>(band, count, st, G, U, nrhs, conj, s);
+    return hipErrorInvalidValue;
+}
+
 template <class R>
 hipError_t launch_sweep(const void* band, int count, const Stencil& st, const double* G, double* U, int nrhs, int conj,
                         hipStream_t s) {
-    constexpr int NB = 16;
-    if (st.n <= 256) return launch_sweep_ks<R, NB, 1>(band, count, st, G, U, nrhs, conj, s);
-    if (st.n <= 512) return launch_sweep_ks<R, NB, 2>(band, count, st, G, U, nrhs, conj, s);
-    if (st.n <= 1024) return launch_sweep_ks<R, NB, 4>(band, count, st, G, U, nrhs, conj, s);
+    if (st.n <= 256) return launch_sweep_kq<R, 1>(band, count, st, G, U, nrhs, conj, s);
+    if (st.n <= 512) return launch_sweep_kq<R, 2>(band, count, st, G, U, nrhs, conj, s);
+    if (st.n <= 1024) return launch_sweep_kq<R, 4>(band, count, st, G, U, nrhs, conj, s);
     return hipErrorInvalidValue;
 }
 
@@ -617,6 +970,7 @@ hipError_t launch_sweep(const void* band, int count, const Stencil& st, const do
 hipError_t band_fill(int precision, void* band, const double* lambda, int count, const Stencil& st, hipStream_t s) {
     const long long per = (long long)st.m * st.m * (st.n + 1);
     const int bx = (int)std::min<long long>((per + 255) / 256, 2048);
+    (void)per;
     if (precision == 32)
         hipLaunchKernelGGL(k_band_fill<float>, dim3(bx, count), dim3(256), 0, s, (cpx<float>*)band, lambda, st);
     else
@@ -624,19 +978,17 @@ hipError_t band_fill(int precision, void* band, const double* lambda, int count,
     return hipGetLastError();
 }
 
+// Panel width: the widest of 32, 16, 8 columns whose LDS fits in 150 KiB.
 hipError_t ldlt_factor(int precision, void* band, int count, const Stencil& st, int* info, hipStream_t s) {
+    constexpr size_t cap = 150u * 1024u;
     if (precision == 32) {
-        switch (ldlt_nb(st.n, sizeof(cpx<float>))) {
-            case 32: return launch_ldlt<float, 32>(band, count, st, info, s);
-            case 16: return launch_ldlt<float, 16>(band, count, st, info, s);
-            case 8: return launch_ldlt<float, 8>(band, count, st, info, s);
-        }
+        if (ldlt_lds_bytes<float, 32>(st.n) <= cap) return launch_ldlt<float, 32>(band, count, st, info, s);
+        if (ldlt_lds_bytes<float, 16>(st.n) <= cap) return launch_ldlt<float, 16>(band, count, st, info, s);
+        if (ldlt_lds_bytes<float, 8>(st.n) <= cap) return launch_ldlt<float, 8>(band, count, st, info, s);
     } else {
-        switch (ldlt_nb(st.n, sizeof(cpx<double>))) {
-            case 32: return launch_ldlt<double, 32>(band, count, st, info, s);
-            case 16: return launch_ldlt<double, 16>(band, count, st, info, s);
-            case 8: return launch_ldlt<double, 8>(band, count, st, info, s);
-        }
+        if (ldlt_lds_bytes<double, 32>(st.n) <= cap) return launch_ldlt<double, 32>(band, count, st, info, s);
+        if (ldlt_lds_bytes<double, 16>(st.n) <= cap) return launch_ldlt<double, 16>(band, count, st, info, s);
+        if (ldlt_lds_bytes<double, 8>(st.n) <= cap) return launch_ldlt<double, 8>(band, count, st, info, s);
     }
     return hipErrorInvalidValue;
 }
