@@ -59,12 +59,12 @@ def progress(msg):
     sys.stderr.flush()
 
 
-def run_steps(st, torch, inputs, precision, steps, warmup, tol, max_iter):
+def run_steps(st, torch, inputs, precision, steps, warmup, tol, max_iter, refine):
     Mt, Bt, Ms, As, n, F = inputs
     reports = []
 
     def one():
-        h = st.fdm_factor(Mt, Bt, Ms, As, n, precision=precision, tol=tol, max_iter=max_iter)
+        h = st.fdm_factor(Mt, Bt, Ms, As, n, precision=precision, tol=tol, max_iter=max_iter, refine=refine)
         Psi = h.solve(F)
         rep = dict(h.last_report)
         h.close()
@@ -72,7 +72,7 @@ def run_steps(st, torch, inputs, precision, steps, warmup, tol, max_iter):
 
     for i in range(warmup):
         _, rep = one()
-        progress("fp%d warmup %d: %.1f ms, ldlt %.1f ms, %d refinement passes, residual %.2e"
+        progress("fp%d warmup %d: %.1f ms, ldlt %.1f ms, %d extra applications of the inverse, residual %.2e"
                  % (precision, i, rep["ms_total"] + rep["ms_eig"] + rep["ms_factor"], rep["ms_ldlt"],
                     rep["iterations"], rep["rel_residual"]))
     torch.cuda.synchronize()
@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=60)
+    ap.add_argument("--refine", default="gmres", choices=["gmres", "plain"],
+                    help="refinement of the FP32 solve (the FP64 comparison always uses gmres)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-block-stride", type=int, default=2)
@@ -152,7 +154,7 @@ def main():
         h.close()
         return
 
-    ms32, reps32, _ = run_steps(st, torch, inputs, 32, args.steps, args.warmup, args.tol, args.max_iter)
+    ms32, reps32, _ = run_steps(st, torch, inputs, 32, args.steps, args.warmup, args.tol, args.max_iter, args.refine)
     value = wl.dofs / (ms32 / 1000.0)
     avg = lambda reps, k: float(np.mean([r[k] for r in reps]))
     ms_ldlt = avg(reps32, "ms_ldlt")
@@ -165,20 +167,22 @@ def main():
         "dtype": "c64 factors+sweeps, c128 residual/refinement", "data": "synthetic",
         "config": {"workload": "FDM solve, unit square n=%d cells/side (n_x=%d, kd=%d), %d P%d time elements "
                                "on (0,%g) (n_t=%d), %d space-time dofs, 1 rhs, manufactured psi omega=%.4g, "
-                               "FP32 LDL^T + FP64 refinement to %.0e"
-                               % (wl.n, n_x, kd, wl.N_t, wl.p_t, wl.T, wl.n_t, wl.dofs, wl.omega, args.tol),
+                               "FP32 LDL^T + FP64 %s refinement to %.0e"
+                               % (wl.n, n_x, kd, wl.N_t, wl.p_t, wl.T, wl.n_t, wl.dofs, wl.omega,
+                                  "GMRES" if args.refine == "gmres" else "plain", args.tol),
                    "dofs": wl.dofs, "n_x": n_x, "n_t": wl.n_t, "rhs": 1},
         "roofline": {"kernel": "k_ldlt (FP32)", "bound": "mfma", "achieved": achieved,
                      "peak": MFMA_PEAK_TFLOPS[32], "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS[32],
                      "traffic": measured_traffic(32), "flops_per_launch": flops, "ms_per_launch": ms_ldlt},
         "stages_ms_fp32": {k: avg(reps32, k) for k in ("ms_eig", "ms_band_fill", "ms_ldlt", "ms_sweeps",
                                                         "ms_transforms", "ms_residual", "ms_factor", "ms_total")},
-        "refinement_fp32": {"iterations": [r["iterations"] for r in reps32],
-                            "rel_residual": [r["rel_residual"] for r in reps32]},
+        "refinement_fp32": {"method": args.refine, "iterations": [r["iterations"] for r in reps32],
+                            "rel_residual": [r["rel_residual"] for r in reps32],
+                            "history": reps32[-1]["history"]},
         "kappa_x": reps32[-1]["kappa_x"],
     }
     if not args.no_fp64:
-        ms64, reps64, _ = run_steps(st, torch, inputs, 64, args.steps, args.warmup, args.tol, args.max_iter)
+        ms64, reps64, _ = run_steps(st, torch, inputs, 64, args.steps, args.warmup, args.tol, args.max_iter, "gmres")
         v64 = wl.dofs / (ms64 / 1000.0)
         out["fp64"] = {"value": v64, "ms_per_step": ms64,
                        "stages_ms": {k: avg(reps64, k) for k in ("ms_eig", "ms_band_fill", "ms_ldlt", "ms_sweeps",

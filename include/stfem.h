@@ -64,16 +64,33 @@ enum stfem_status {
  * centre, east (+x), west (-x), north (+y), south (-y), north-east, south-west. */
 enum { STFEM_ST_C = 0, STFEM_ST_E, STFEM_ST_W, STFEM_ST_N, STFEM_ST_S, STFEM_ST_NE, STFEM_ST_SW, STFEM_ST_COUNT };
 
+/* Refinement of fdm_solve / fdm_solve_adjoint.  Both form every residual in
+ * FP64 with the Kronecker matvec and precondition with the factored FDM
+ * inverse (FP32 or FP64 factors):
+ *  - STFEM_REFINE_GMRES: flexible GMRES, restarted after `restart` (at most
+ *    23, fewer if the basis would exceed 16 GiB) applications of the inverse,
+ *    with classical Gram-Schmidt applied twice; each cycle ends with a
+ *    recomputed residual;
+ *  - STFEM_REFINE_PLAIN: classical iterative refinement,
+ *    Psi <- Psi + FDM^{-1} (F - K Psi).
+ * GMRES contracts much faster when a few spatial blocks are ill conditioned
+ * in FP32, because their error lives in a few directions that the Krylov
+ * space removes. */
+enum { STFEM_REFINE_GMRES = 0, STFEM_REFINE_PLAIN = 1 };
+
 typedef struct stfem_options {
     int precision;      /* 32: complex FP32 factors and sweeps, FP64 refinement;
                            64: complex FP64 factors and sweeps                     */
-    int max_iter;       /* refinement passes after the first solve (>= 0)         */
+    int max_iter;       /* applications of the FDM inverse beyond the first (>= 0) */
     double tol;         /* target ||F - K Psi||_2 / ||F||_2, per right-hand side;
                            <= 0 disables the residual check (single pass)          */
+    int refine;         /* STFEM_REFINE_GMRES (0, default) or STFEM_REFINE_PLAIN   */
+    int restart;        /* GMRES: applications of the inverse per cycle before a
+                           restart; 0 = automatic (1 + max_iter, at most 23)       */
 } stfem_options;
 
 typedef struct stfem_report {
-    int iterations;         /* refinement passes taken (0 = the first solve only) */
+    int iterations;         /* applications of the FDM inverse beyond the first   */
     double rel_residual;    /* max over rhs of ||F - K Psi||_2 / ||F||_2 (FP64)   */
     double kappa_x;         /* estimate of kappa_2(X), unit 2-norm columns        */
     double ms_eig;          /* host temporal eigen-step (fdm_factor)              */
@@ -86,8 +103,9 @@ typedef struct stfem_report {
     double ms_sweeps;       /* all sweep kernels of this call                     */
     double ms_transforms;   /* all temporal-transform GEMM kernels of this call   */
     double ms_residual;     /* all residual kernels of this call                  */
-    double history[16];     /* relative residual after each of the first 16 passes
-                               (unused entries are -1)                             */
+    double history[16];     /* relative residual after each of the first 16
+                               applications of the inverse (GMRES: its own
+                               estimate; unused entries are -1)                    */
 } stfem_report;
 
 typedef struct stfem_handle stfem_handle;   /* FDM solver: X, W, lambda, factors */
@@ -147,11 +165,14 @@ int fdm_factor(const double* M_t, const double* B_t, int n_t,
                const stfem_options* opt, void* stream, stfem_handle** out);
 
 /* Solve K Psi = F for nrhs right-hand sides.  F_dev, Psi_dev: device
- * complex128 [nrhs][n_t][n_x]; they must not overlap.  Steps: G = W F,
- * batched sweeps, Psi = X U; then, while the FP64 relative residual of some
- * rhs exceeds opt.tol and fewer than opt.max_iter passes were taken,
- * R = F - K Psi, Psi += X S^{-1} W R.  rep (may be NULL) receives statistics.
- * Returns ENOCONV (Psi still holds the best iterate) if tol was not met. */
+ * complex128 [nrhs][n_t][n_x]; they must not overlap.  One application of the
+ * FDM inverse is G = W F, batched sweeps, Psi = X U.  With opt.tol > 0 the
+ * solve is refined (opt.refine) until the FP64 relative residual of every rhs
+ * is <= opt.tol or 1 + opt.max_iter inverses were applied.  The GMRES
+ * refinement allocates its Krylov basis on the first call that needs it (at
+ * most 2 KRYLOV_MAX vectors of nrhs n_t n_x complex128, capped at 16 GiB) and
+ * keeps it with the handle.  rep (may be NULL) receives statistics.  Returns
+ * ENOCONV (Psi still holds the last iterate) if tol was not met. */
 int fdm_solve(stfem_handle* h, const void* F_dev, void* Psi_dev, int nrhs,
               void* stream, stfem_report* rep);
 

@@ -81,7 +81,10 @@ def fdm_temporal(M_t, B_t):
 class FDM:
     """Owner of a factored Kronecker system (stfem_handle)."""
 
-    def __init__(self, M_t, B_t, M_st, A_st, n, precision=64, tol=1e-10, max_iter=30, stream=None):
+    REFINE = {"gmres": 0, "plain": 1}
+
+    def __init__(self, M_t, B_t, M_st, A_st, n, precision=64, tol=1e-10, max_iter=30, stream=None, refine="gmres",
+                 restart=0):
         M_t = np.ascontiguousarray(M_t, dtype=np.float64)
         B_t = np.ascontiguousarray(B_t, dtype=np.float64)
         M_st = np.ascontiguousarray(M_st, dtype=np.float64)
@@ -89,7 +92,9 @@ class FDM:
         nt = M_t.shape[0]
         if M_t.shape != (nt, nt) or B_t.shape != (nt, nt):
             raise ValueError("temporal matrices must be square and equal in size")
-        opt = Options(int(precision), int(max_iter), float(tol))
+        if refine not in self.REFINE:
+            raise ValueError("refine must be one of %s" % sorted(self.REFINE))
+        opt = Options(int(precision), int(max_iter), float(tol), self.REFINE[refine], int(restart))
         h = ctypes.c_void_p()
         check(lib().fdm_factor(dptr(M_t), dptr(B_t), nt, dptr(M_st), dptr(A_st), int(n), ctypes.byref(opt),
                                _stream(stream), ctypes.byref(h)))
@@ -156,8 +161,9 @@ class FDM:
             pass
 
 
-def fdm_factor(M_t, B_t, M_st, A_st, n, precision=64, tol=1e-10, max_iter=30, stream=None):
-    return FDM(M_t, B_t, M_st, A_st, n, precision, tol, max_iter, stream)
+def fdm_factor(M_t, B_t, M_st, A_st, n, precision=64, tol=1e-10, max_iter=30, stream=None, refine="gmres",
+               restart=0):
+    return FDM(M_t, B_t, M_st, A_st, n, precision, tol, max_iter, stream, refine, restart)
 
 
 def fdm_solve(h, F, out=None, stream=None):

@@ -25,7 +25,8 @@ class StfemError(RuntimeError):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double)]
+    _fields_ = [("precision", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
+                ("refine", ctypes.c_int), ("restart", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):

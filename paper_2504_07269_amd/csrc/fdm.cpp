@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -96,6 +97,13 @@ struct stfem_handle {
     double* G_ws = nullptr;
     double* R_ws = nullptr;
     size_t ws_elems = 0;          // complex elements of each of G_ws, R_ws
+    // GMRES refinement: basis V_0..V_m then Z_0..Z_{m-1}, each nrhs n_t n_x
+    // complex128; small device arrays for coefficients and norms
+    double* kry = nullptr;
+    size_t kry_bytes = 0;
+    int kry_nrhs = 0, kry_m = 0;
+    double* kry_partial = nullptr;
+    double* kry_small = nullptr;  // coef1, coef2 [nrhs][KRYLOV_MAX] complex; nrm, sc [nrhs]
     double* partial = nullptr;
     size_t partial_elems = 0;
     double* norms_dev = nullptr;
@@ -106,11 +114,12 @@ struct stfem_handle {
 
 namespace {
 
-// Factor storage runs to tens of GB; allocating and releasing it costs
-// hundreds of milliseconds.  Released factor buffers of >= 64 MiB are kept
-// (at most two per device) and handed to the next factorisation that fits in
-// them without wasting more than a quarter; stfem_release_cache() returns
-// them to the device.
+// Factor storage runs to tens of GB and the solve workspaces to several;
+// allocating and releasing them costs milliseconds per GB.  Released buffers
+// of >= 64 MiB are kept (at most CACHE_PER_DEVICE per device) and handed to
+// the next request that fits in them without wasting more than a quarter; a
+// failed allocation first gives them all back, and stfem_release_cache()
+// returns them to the device.
 struct CachedBuffer {
     void* ptr;
     size_t bytes;
@@ -119,13 +128,14 @@ struct CachedBuffer {
 std::mutex g_cache_mutex;
 std::vector<CachedBuffer> g_cache;
 constexpr size_t CACHE_MIN_BYTES = (size_t)64 << 20;
+constexpr int CACHE_PER_DEVICE = 6;
 
 void release_cache_locked() {
     for (auto& c : g_cache) (void)hipFree(c.ptr);
     g_cache.clear();
 }
 
-hipError_t factor_alloc(void** p, size_t bytes) {
+hipError_t cached_alloc(void** p, size_t bytes) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     {
@@ -149,7 +159,7 @@ hipError_t factor_alloc(void** p, size_t bytes) {
     return e;
 }
 
-void factor_free(void* p, size_t bytes) {
+void cached_free(void* p, size_t bytes) {
     if (!p) return;
     if (bytes < CACHE_MIN_BYTES) {
         (void)hipFree(p);
@@ -160,7 +170,7 @@ void factor_free(void* p, size_t bytes) {
     std::lock_guard<std::mutex> lk(g_cache_mutex);
     int same = 0;
     for (auto& c : g_cache) same += (c.device == dev);
-    if (same >= 2) {   // drop the oldest buffer of this device
+    if (same >= CACHE_PER_DEVICE) {   // drop the oldest buffer of this device
         for (size_t i = 0; i < g_cache.size(); ++i)
             if (g_cache[i].device == dev) {
                 (void)hipFree(g_cache[i].ptr);
@@ -196,7 +206,7 @@ size_t elem_bytes(int precision) { return precision == 32 ? 8 : 16; }
 void free_blocks(stfem_blocks* b) {
     if (!b) return;
     b->timer.release();
-    factor_free(b->band, b->band_bytes);
+    cached_free(b->band, b->band_bytes);
     if (b->info) (void)hipFree(b->info);
     if (b->lambda_dev) (void)hipFree(b->lambda_dev);
     delete b;
@@ -224,7 +234,7 @@ int blocks_launch(int n, const double* Ms, const double* As, const double* lambd
     b->lambda.assign(lambda, lambda + 2 * count);
     const size_t bytes = (size_t)count * gpu::band_stride_host(n) * elem_bytes(precision);
     b->band_bytes = bytes;
-    if (factor_alloc(&b->band, bytes) != hipSuccess) {
+    if (cached_alloc(&b->band, bytes) != hipSuccess) {
         (void)hipGetLastError();
         b->band = nullptr;
         free_blocks(b);
@@ -272,13 +282,14 @@ int blocks_finish(stfem_blocks* b, hipStream_t s) {
 int ensure_workspace(stfem_handle* h, int nrhs) {
     const size_t need = (size_t)nrhs * h->n_t * h->n_x;
     if (need > h->ws_elems) {
-        if (h->G_ws) (void)hipFree(h->G_ws);
-        if (h->R_ws) (void)hipFree(h->R_ws);
+        cached_free(h->G_ws, h->ws_elems * 16);
+        cached_free(h->R_ws, h->ws_elems * 16);
         h->G_ws = h->R_ws = nullptr;
         h->ws_elems = 0;
-        if (hipMalloc(&h->G_ws, need * 16) != hipSuccess || hipMalloc(&h->R_ws, need * 16) != hipSuccess) {
+        if (cached_alloc((void**)&h->G_ws, need * 16) != hipSuccess ||
+            cached_alloc((void**)&h->R_ws, need * 16) != hipSuccess) {
             (void)hipGetLastError();
-            if (h->G_ws) (void)hipFree(h->G_ws);
+            cached_free(h->G_ws, need * 16);
             h->G_ws = h->R_ws = nullptr;
             return fail(STFEM_ENOMEM, "solve workspace allocation failed");
         }
@@ -344,6 +355,199 @@ int apply_inverse(stfem_handle* h, const double* in, double* out, int nrhs, int 
     return STFEM_OK;
 }
 
+// ------------------------------------------------------- GMRES refinement
+// Krylov storage for nrhs right-hand sides: 2m+1 arrays of nrhs n_t n_x
+// complex128, m <= KRYLOV_MAX - 1 and within KRYLOV_BUDGET.
+constexpr size_t KRYLOV_BUDGET = (size_t)16 << 30;
+
+int ensure_krylov(stfem_handle* h, int nrhs) {
+    const size_t vec = (size_t)nrhs * h->n_t * h->n_x * 16;
+    const size_t fit = KRYLOV_BUDGET / vec >= 3 ? (KRYLOV_BUDGET / vec - 1) / 2 : 1;
+    const size_t want = h->opt.restart > 0 ? (size_t)h->opt.restart : (size_t)h->opt.max_iter + 1;
+    const int m = (int)std::max<size_t>(1, std::min<size_t>({want, (size_t)gpu::KRYLOV_MAX - 1, fit}));
+    const size_t need = (2 * (size_t)m + 1) * vec;
+    if (need > h->kry_bytes) {
+        cached_free(h->kry, h->kry_bytes);
+        h->kry = nullptr;
+        h->kry_bytes = 0;
+        if (cached_alloc((void**)&h->kry, need) != hipSuccess) {
+            (void)hipGetLastError();
+            h->kry = nullptr;
+            return fail(STFEM_ENOMEM, "Krylov basis allocation failed");
+        }
+        h->kry_bytes = need;
+    }
+    if (nrhs > h->kry_nrhs) {
+        if (h->kry_partial) (void)hipFree(h->kry_partial);
+        if (h->kry_small) (void)hipFree(h->kry_small);
+        h->kry_partial = h->kry_small = nullptr;
+        h->kry_nrhs = 0;
+        if (hipMalloc(&h->kry_partial, gpu::krylov_partial_size(nrhs) * sizeof(double)) != hipSuccess ||
+            hipMalloc(&h->kry_small, ((size_t)4 * gpu::KRYLOV_MAX + 2) * nrhs * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(STFEM_ENOMEM, "Krylov scratch allocation failed");
+        }
+        h->kry_nrhs = nrhs;
+    }
+    h->kry_m = m;
+    return STFEM_OK;
+}
+
+typedef std::complex<double> zd;
+
+// Flexible GMRES on K Psi = F (adjoint: K^H) with the FDM inverse as right
+// preconditioner, started from Psi = 0 and restarted every m columns; each
+// rhs has its own Hessenberg matrix, all rhs share the batched kernels.  Every
+// residual and basis vector is FP64; the preconditioner runs in the factor
+// precision.  Orthogonalisation: classical Gram-Schmidt, twice.
+int refine_gmres(stfem_handle* h, const double* F, double* Psi, int nrhs, int adjoint, hipStream_t s, int& applied,
+                 double& rel, double* hist) {
+    int st = ensure_krylov(h, nrhs);
+    if (st) return st;
+    const int m = h->kry_m, KM = gpu::KRYLOV_MAX;
+    const long long N = (long long)h->n_t * h->n_x;
+    const long long vs = (long long)nrhs * N;                  // complex elements per basis array
+    double* V = h->kry;
+    double* Z = h->kry + 2 * (size_t)(m + 1) * vs;
+    auto Vp = [&](int i) { return V + 2 * (size_t)i * vs; };
+    auto Zp = [&](int i) { return Z + 2 * (size_t)i * vs; };
+    double* coef1 = h->kry_small;                              // [nrhs][KM] complex
+    double* coef2 = coef1 + 2 * (size_t)KM * nrhs;
+    double* nrm = coef2 + 2 * (size_t)KM * nrhs;               // [nrhs]
+    double* sc = nrm + nrhs;                                   // [nrhs]
+    double* part = h->kry_partial;
+    StageTimer& T = h->timer;
+    const int max_apply = 1 + h->opt.max_iter;
+    const double tol = h->opt.tol;
+
+    std::vector<double> fn(nrhs), beta(nrhs), nh(nrhs), sh(nrhs);
+    std::vector<double> c1(2 * (size_t)KM * nrhs), c2(2 * (size_t)KM * nrhs);
+    HIPCHECK(T.begin(s));
+    HIPCHECK(gpu::vec_norm2(F, N, nrhs, part, nrm, s));
+    HIPCHECK(T.end(s, StageTimer::RESID));
+    HIPCHECK(hipMemcpyAsync(fn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    for (int r = 0; r < nrhs; ++r) beta[r] = fn[r] = std::sqrt(fn[r]);
+
+    std::vector<zd> H((size_t)nrhs * (m + 1) * m), g((size_t)nrhs * (m + 1)), sn((size_t)nrhs * m);
+    std::vector<double> cs((size_t)nrhs * m);
+    auto Hat = [&](int r, int i, int j) -> zd& { return H[((size_t)r * (m + 1) + i) * m + j]; };
+    const double* r0 = F;
+    bool first = true;
+    applied = 0;
+    rel = INFINITY;
+    for (;;) {
+        // V_0 = r0 / beta
+        for (int r = 0; r < nrhs; ++r) sh[r] = beta[r] > 0 && std::isfinite(beta[r]) ? 1.0 / beta[r] : 0.0;
+        HIPCHECK(hipMemcpyAsync(sc, sh.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+        HIPCHECK(T.begin(s));
+        HIPCHECK(gpu::vec_scale(Vp(0), r0, N, nrhs, sc, s));
+        HIPCHECK(T.end(s, StageTimer::RESID));
+        std::fill(H.begin(), H.end(), zd(0));
+        std::fill(g.begin(), g.end(), zd(0));
+        for (int r = 0; r < nrhs; ++r) g[(size_t)r * (m + 1)] = beta[r];
+        int ncol = 0;
+        while (ncol < m && applied < max_apply) {
+            const int j = ncol;
+            st = apply_inverse(h, Vp(j), Zp(j), nrhs, adjoint, 0, s);
+            if (st) return st;
+            ++applied;
+            HIPCHECK(T.begin(s));
+            HIPCHECK(gpu::kron_apply(Zp(j), Vp(j + 1), nrhs, h->n_t, h->w, h->tM_dev, h->tB_dev, h->blk->st, adjoint,
+                                     s));
+            HIPCHECK(gpu::vec_mdot(V, vs, j + 1, Vp(j + 1), N, nrhs, part, coef1, s));
+            HIPCHECK(gpu::vec_mcomb(Vp(j + 1), N, nrhs, V, vs, j + 1, coef1, -1.0, 1, part, nullptr, s));
+            HIPCHECK(gpu::vec_mdot(V, vs, j + 1, Vp(j + 1), N, nrhs, part, coef2, s));
+            HIPCHECK(gpu::vec_mcomb(Vp(j + 1), N, nrhs, V, vs, j + 1, coef2, -1.0, 1, part, nrm, s));
+            HIPCHECK(T.end(s, StageTimer::RESID));
+            const size_t cb = sizeof(double) * 2 * (size_t)(j + 1) * nrhs;
+            HIPCHECK(hipMemcpyAsync(c1.data(), coef1, cb, hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipMemcpyAsync(c2.data(), coef2, cb, hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipMemcpyAsync(nh.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipStreamSynchronize(s));
+            double est = 0;
+            for (int r = 0; r < nrhs; ++r) {
+                for (int i = 0; i <= j; ++i) {
+                    const size_t q = 2 * ((size_t)r * (j + 1) + i);
+                    Hat(r, i, j) = zd(c1[q] + c2[q], c1[q + 1] + c2[q + 1]);
+                }
+                const double hn = std::sqrt(nh[r]);
+                sh[r] = hn > 0 && std::isfinite(1.0 / hn) ? 1.0 / hn : 0.0;
+                // previous rotations, then the one that zeroes H[j+1][j]
+                for (int i = 0; i < j; ++i) {
+                    const double c = cs[(size_t)r * m + i];
+                    const zd sv = sn[(size_t)r * m + i];
+                    const zd a = Hat(r, i, j), b = Hat(r, i + 1, j);
+                    Hat(r, i, j) = c * a + sv * b;
+                    Hat(r, i + 1, j) = -std::conj(sv) * a + c * b;
+                }
+                const zd a = Hat(r, j, j);
+                const double rho = std::hypot(std::abs(a), hn);
+                double c = 1.0;
+                zd sv = 0.0;
+                if (rho > 0) {
+                    if (std::abs(a) > 0) {
+                        c = std::abs(a) / rho;
+                        sv = (a / std::abs(a)) * hn / rho;
+                    } else {
+                        c = 0.0;
+                        sv = 1.0;
+                    }
+                }
+                cs[(size_t)r * m + j] = c;
+                sn[(size_t)r * m + j] = sv;
+                Hat(r, j, j) = c * a + sv * hn;
+                zd& gj = g[(size_t)r * (m + 1) + j];
+                g[(size_t)r * (m + 1) + j + 1] = -std::conj(sv) * gj;
+                gj = c * gj;
+                if (fn[r] > 0) est = std::max(est, std::abs(g[(size_t)r * (m + 1) + j + 1]) / fn[r]);
+            }
+            HIPCHECK(hipMemcpyAsync(sc, sh.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+            HIPCHECK(T.begin(s));
+            HIPCHECK(gpu::vec_scale(Vp(j + 1), Vp(j + 1), N, nrhs, sc, s));
+            HIPCHECK(T.end(s, StageTimer::RESID));
+            if (applied <= 16) hist[applied - 1] = est;
+            ++ncol;
+            if (!(est > 0.5 * tol)) break;      // also stops on NaN
+        }
+        // y = R^{-1} g per rhs, then Psi (+)= Z y
+        for (int r = 0; r < nrhs; ++r) {
+            std::vector<zd> y(ncol);
+            for (int i = ncol - 1; i >= 0; --i) {
+                zd t = g[(size_t)r * (m + 1) + i];
+                for (int k = i + 1; k < ncol; ++k) t -= Hat(r, i, k) * y[k];
+                const zd d = Hat(r, i, i);
+                y[i] = std::abs(d) > 0 ? t / d : zd(0);
+            }
+            for (int i = 0; i < ncol; ++i) {
+                c1[2 * ((size_t)r * ncol + i)] = y[i].real();
+                c1[2 * ((size_t)r * ncol + i) + 1] = y[i].imag();
+            }
+        }
+        HIPCHECK(hipMemcpyAsync(coef1, c1.data(), sizeof(double) * 2 * (size_t)ncol * nrhs, hipMemcpyHostToDevice, s));
+        HIPCHECK(T.begin(s));
+        HIPCHECK(gpu::vec_mcomb(Psi, N, nrhs, Z, vs, ncol, coef1, 1.0, first ? 0 : 1, part, nullptr, s));
+        first = false;
+        // recomputed residual
+        HIPCHECK(gpu::kron_residual(Psi, F, h->R_ws, nrhs, h->n_t, h->w, h->tM_dev, h->tB_dev, h->blk->st, adjoint,
+                                    h->partial, h->norms_dev, s));
+        HIPCHECK(T.end(s, StageTimer::RESID));
+        std::vector<double> nv(2 * (size_t)nrhs);
+        HIPCHECK(hipMemcpyAsync(nv.data(), h->norms_dev, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        rel = 0;
+        for (int r = 0; r < nrhs; ++r) {
+            beta[r] = std::sqrt(nv[2 * r]);
+            const double v = fn[r] > 0 ? beta[r] / fn[r] : (beta[r] > 0 ? INFINITY : 0.0);
+            rel = std::max(rel, std::isfinite(v) ? v : INFINITY);
+        }
+        if (applied >= 1 && applied <= 16) hist[applied - 1] = rel;
+        if (rel <= tol || applied >= max_apply || !std::isfinite(rel)) break;
+        r0 = h->R_ws;
+    }
+    return STFEM_OK;
+}
+
 int solve_common(stfem_handle* h, const void* F_dev, void* Psi_dev, int nrhs, void* stream, stfem_report* rep,
                  int adjoint) {
     clear_error();
@@ -356,25 +560,32 @@ int solve_common(stfem_handle* h, const void* F_dev, void* Psi_dev, int nrhs, vo
     if (st) return st;
     const double* F = (const double*)F_dev;
     double* Psi = (double*)Psi_dev;
-    st = apply_inverse(h, F, Psi, nrhs, adjoint, 0, s);
-    if (st) return st;
     int it = 0;
     double rel = -1.0;
     double hist[16];
     for (double& x : hist) x = -1.0;
-    if (h->opt.tol > 0) {
-        for (;;) {
-            HIPCHECK(h->timer.begin(s));
-            HIPCHECK(gpu::kron_residual(Psi, F, h->R_ws, nrhs, h->n_t, h->w, h->tM_dev, h->tB_dev, h->blk->st, adjoint,
-                                        h->partial, h->norms_dev, s));
-            HIPCHECK(h->timer.end(s, StageTimer::RESID));
-            st = read_relres(h, nrhs, s, rel);
-            if (st) return st;
-            if (it < 16) hist[it] = rel;
-            if (rel <= h->opt.tol || it >= h->opt.max_iter || !std::isfinite(rel)) break;
-            st = apply_inverse(h, h->R_ws, Psi, nrhs, adjoint, 1, s);
-            if (st) return st;
-            ++it;
+    if (h->opt.tol > 0 && h->opt.refine == STFEM_REFINE_GMRES) {
+        int applied = 0;
+        st = refine_gmres(h, F, Psi, nrhs, adjoint, s, applied, rel, hist);
+        if (st) return st;
+        it = applied - 1;
+    } else {
+        st = apply_inverse(h, F, Psi, nrhs, adjoint, 0, s);
+        if (st) return st;
+        if (h->opt.tol > 0) {
+            for (;;) {
+                HIPCHECK(h->timer.begin(s));
+                HIPCHECK(gpu::kron_residual(Psi, F, h->R_ws, nrhs, h->n_t, h->w, h->tM_dev, h->tB_dev,
+                                            h->blk->st, adjoint, h->partial, h->norms_dev, s));
+                HIPCHECK(h->timer.end(s, StageTimer::RESID));
+                st = read_relres(h, nrhs, s, rel);
+                if (st) return st;
+                if (it < 16) hist[it] = rel;
+                if (rel <= h->opt.tol || it >= h->opt.max_iter || !std::isfinite(rel)) break;
+                st = apply_inverse(h, h->R_ws, Psi, nrhs, adjoint, 1, s);
+                if (st) return st;
+                ++it;
+            }
         }
     }
     HIPCHECK(hipStreamSynchronize(s));
@@ -396,8 +607,9 @@ int solve_common(stfem_handle* h, const void* F_dev, void* Psi_dev, int nrhs, vo
     }
     if (h->opt.tol > 0 && !(rel <= h->opt.tol)) {
         char msg[160];
-        std::snprintf(msg, sizeof msg, "refinement stopped at relative residual %.3e (tolerance %.3e) after %d passes",
-                      rel, h->opt.tol, it);
+        std::snprintf(msg, sizeof msg,
+                      "refinement stopped at relative residual %.3e (tolerance %.3e) after %d applications of the "
+                      "inverse", rel, h->opt.tol, it + 1);
         return fail(STFEM_ENOCONV, msg);
     }
     return STFEM_OK;
@@ -471,10 +683,13 @@ extern "C" int fdm_factor(const double* M_t, const double* B_t, int n_t, const d
     if (!out) return fail(STFEM_EINVAL, "fdm_factor: null output handle");
     *out = nullptr;
     if (!M_t || !B_t || n_t < 1) return fail(STFEM_EINVAL, "fdm_factor: null temporal matrices or n_t < 1");
-    stfem_options o{64, 0, 0.0};
+    stfem_options o{64, 0, 0.0, STFEM_REFINE_GMRES, 0};
     if (opt) o = *opt;
     if (o.precision != 32 && o.precision != 64) return fail(STFEM_EINVAL, "fdm_factor: precision must be 32 or 64");
     if (o.max_iter < 0) return fail(STFEM_EINVAL, "fdm_factor: max_iter must be >= 0");
+    if (o.refine != STFEM_REFINE_GMRES && o.refine != STFEM_REFINE_PLAIN)
+        return fail(STFEM_EINVAL, "fdm_factor: refine must be STFEM_REFINE_GMRES or STFEM_REFINE_PLAIN");
+    if (o.restart < 0) return fail(STFEM_EINVAL, "fdm_factor: restart must be >= 0");
     hipStream_t s = (hipStream_t)stream;
     const double t0 = now_ms();
     auto* h = new stfem_handle();
@@ -575,7 +790,11 @@ extern "C" void fdm_destroy(stfem_handle* h) {
     if (!h) return;
     h->timer.release();
     free_blocks(h->blk);
-    for (double* p : {h->X_dev, h->W_dev, h->tM_dev, h->tB_dev, h->G_ws, h->R_ws, h->partial, h->norms_dev})
+    cached_free(h->G_ws, h->ws_elems * 16);
+    cached_free(h->R_ws, h->ws_elems * 16);
+    cached_free(h->kry, h->kry_bytes);
+    for (double* p : {h->X_dev, h->W_dev, h->tM_dev, h->tB_dev, h->partial, h->norms_dev, h->kry_partial,
+                      h->kry_small})
         if (p) (void)hipFree(p);
     delete h;
 }

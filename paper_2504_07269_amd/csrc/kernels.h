@@ -58,6 +58,24 @@ hipError_t kron_apply(const double* Psi, double* Y, int nrhs, int n_t, int w, co
 hipError_t spatial_apply(const Stencil& st, double ar, double ai, double br, double bi, const double* X,
                          double* Y, int count, hipStream_t s);
 
+// Krylov vectors of the refinement: complex128, nrhs slices of N elements;
+// a basis of nv vectors vstride complex elements apart (nv <= KRYLOV_MAX).
+// `partial` holds >= krylov_partial_size(nrhs) doubles of scratch.
+constexpr int KRYLOV_MAX = 24;
+constexpr int VEC_BLOCKS = 1024;
+size_t krylov_partial_size(int nrhs);
+// out[r][i] = <V_i[r], w[r]> = sum_e conj(V_i[r][e]) w[r][e]   (complex, device)
+hipError_t vec_mdot(const double* V, long long vstride, int nv, const double* w, long long N, int nrhs,
+                    double* partial, double* out, hipStream_t s);
+// w[r] = (accumulate ? w[r] : 0) + sign sum_i coef[r][i] V_i[r]; coef complex
+// [nrhs][nv] on the device; norms[r] = ||w[r]||^2 afterwards if norms != null.
+hipError_t vec_mcomb(double* w, long long N, int nrhs, const double* V, long long vstride, int nv, const double* coef,
+                     double sign, int accumulate, double* partial, double* norms, hipStream_t s);
+// norms[r] = ||x[r]||^2
+hipError_t vec_norm2(const double* x, long long N, int nrhs, double* partial, double* norms, hipStream_t s);
+// y[r] = sc[r] x[r], sc real [nrhs] on the device; y may equal x
+hipError_t vec_scale(double* y, const double* x, long long N, int nrhs, const double* sc, hipStream_t s);
+
 // p[0..count) = value (a kernel, so that it may be recorded in a graph).
 hipError_t fill_int(int* p, int count, int value, hipStream_t s);
 

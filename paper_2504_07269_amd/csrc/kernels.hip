@@ -869,6 +869,133 @@ __global__ __launch_bounds__(256) void k_spatial(const double2* __restrict__ X, 
                                ar * Mv.y + ai * Mv.x + br * Av.y + bi * Av.x);
 }
 
+// ------------------------------------------------------------- Krylov vectors
+// Space-time vectors of the refinement: complex128, nrhs slices of N
+// elements (slice r at offset r*N).  A basis holds nv such vectors, vstride
+// complex elements apart.  Every reduction runs over VEC_BLOCKS workgroups per
+// rhs, then k_partial_reduce sums their partial results.
+
+// Sum of a 64-lane wave, then of the 4 waves of a 256-thread workgroup
+// (result valid in thread 0).  `red` holds 4 doubles.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+// partial[(r*VEC_BLOCKS + bx)*2nv + 2i + {0,1}] = workgroup share of
+// sum_e conj(V_i[r][e]) w[r][e]
+__global__ __launch_bounds__(256) void k_mdot(const double2* __restrict__ V, long long vstride, int nv,
+                                              const double2* __restrict__ w, long long N,
+                                              double* __restrict__ partial) {
+    const int r = blockIdx.y;
+    const double2* wr = w + (size_t)r * N;
+    const double2* Vr = V + (size_t)r * N;
+    double2 acc[KRYLOV_MAX];
+#pragma unroll
+    for (int i = 0; i < KRYLOV_MAX; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long long)VEC_BLOCKS * 256) {
+        const double2 x = wr[e];
+#pragma unroll
+        for (int i = 0; i < KRYLOV_MAX; ++i) {
+            if (i < nv) {
+                const double2 v = Vr[(size_t)i * vstride + e];
+                acc[i].x += v.x * x.x + v.y * x.y;
+                acc[i].y += v.x * x.y - v.y * x.x;
+            }
+        }
+    }
+    __shared__ double red[4];
+    double* out = partial + ((size_t)r * VEC_BLOCKS + blockIdx.x) * 2 * nv;
+#pragma unroll
+    for (int i = 0; i < KRYLOV_MAX; ++i) {
+        if (i < nv) {
+            const double re = block_sum(acc[i].x, red);
+            const double im = block_sum(acc[i].y, red);
+            if (threadIdx.x == 0) {
+                out[2 * i] = re;
+                out[2 * i + 1] = im;
+            }
+        }
+    }
+}
+
+// w[r] = (accumulate ? w[r] : 0) + sign * sum_i coef[r][i] V_i[r]; with
+// partial != null also the workgroup shares of ||w[r]||^2 (new values).
+__global__ __launch_bounds__(256) void k_mcomb(double2* __restrict__ w, long long N, const double2* __restrict__ V,
+                                               long long vstride, int nv, const double2* __restrict__ coef,
+                                               double sign, int accumulate, double* __restrict__ partial) {
+    const int r = blockIdx.y;
+    double2* wr = w + (size_t)r * N;
+    const double2* Vr = V + (size_t)r * N;
+    __shared__ double2 c[KRYLOV_MAX];
+    if (threadIdx.x < nv) {
+        const double2 v = coef[(size_t)r * nv + threadIdx.x];
+        c[threadIdx.x] = make_double2(sign * v.x, sign * v.y);
+    }
+    __syncthreads();
+    double nrm = 0.0;
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long long)VEC_BLOCKS * 256) {
+        double2 x = accumulate ? wr[e] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < KRYLOV_MAX; ++i) {
+            if (i < nv) {
+                const double2 v = Vr[(size_t)i * vstride + e];
+                x.x += c[i].x * v.x - c[i].y * v.y;
+                x.y += c[i].x * v.y + c[i].y * v.x;
+            }
+        }
+        wr[e] = x;
+        nrm += x.x * x.x + x.y * x.y;
+    }
+    if (partial) {
+        __shared__ double red[4];
+        const double t = block_sum(nrm, red);
+        if (threadIdx.x == 0) partial[(size_t)r * VEC_BLOCKS + blockIdx.x] = t;
+    }
+}
+
+// workgroup shares of ||x[r]||^2
+__global__ __launch_bounds__(256) void k_vnorm2(const double2* __restrict__ x, long long N,
+                                                double* __restrict__ partial) {
+    const int r = blockIdx.y;
+    const double2* xr = x + (size_t)r * N;
+    double nrm = 0.0;
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long long)VEC_BLOCKS * 256) {
+        const double2 v = xr[e];
+        nrm += v.x * v.x + v.y * v.y;
+    }
+    __shared__ double red[4];
+    const double t = block_sum(nrm, red);
+    if (threadIdx.x == 0) partial[(size_t)r * VEC_BLOCKS + blockIdx.x] = t;
+}
+
+// y[r] = sc[r] x[r] (sc real, on the device); y may equal x
+__global__ __launch_bounds__(256) void k_vscale(double2* y, const double2* x, long long N, const double* sc) {
+    const int r = blockIdx.y;
+    const double a = sc[r];
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long long)VEC_BLOCKS * 256) {
+        const double2 v = x[(size_t)r * N + e];
+        y[(size_t)r * N + e] = make_double2(a * v.x, a * v.y);
+    }
+}
+
+// out[r*width + c] = sum over the VEC_BLOCKS shares partial[(r*VEC_BLOCKS + b)*width + c]
+__global__ __launch_bounds__(256) void k_partial_reduce(const double* __restrict__ partial, int width,
+                                                        double* __restrict__ out) {
+    const int r = blockIdx.x;
+    __shared__ double red[4];
+    for (int c = 0; c < width; ++c) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < VEC_BLOCKS; b += 256) v += partial[((size_t)r * VEC_BLOCKS + b) * width + c];
+        const double t = block_sum(v, red);
+        if (threadIdx.x == 0) out[(size_t)r * width + c] = t;
+    }
+}
+
 __global__ void k_fill_int(int* p, int count, int value) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = value;
@@ -1039,6 +1166,43 @@ hipError_t spatial_apply(const Stencil& st, double ar, double ai, double br, dou
     const int n_x = st.m * st.m;
     hipLaunchKernelGGL(k_spatial, dim3((n_x + 255) / 256, count), dim3(256), 0, s, (const double2*)X, (double2*)Y, st,
                        ar, ai, br, bi);
+    return hipGetLastError();
+}
+
+size_t krylov_partial_size(int nrhs) { return (size_t)nrhs * VEC_BLOCKS * 2 * KRYLOV_MAX; }
+
+hipError_t vec_mdot(const double* V, long long vstride, int nv, const double* w, long long N, int nrhs,
+                    double* partial, double* out, hipStream_t s) {
+    if (nv < 1 || nv > KRYLOV_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mdot, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, s, (const double2*)V, vstride, nv,
+                       (const double2*)w, N, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_partial_reduce, dim3(nrhs), dim3(256), 0, s, (const double*)partial, 2 * nv, out);
+    return hipGetLastError();
+}
+
+hipError_t vec_mcomb(double* w, long long N, int nrhs, const double* V, long long vstride, int nv, const double* coef,
+                     double sign, int accumulate, double* partial, double* norms, hipStream_t s) {
+    if (nv < 0 || nv > KRYLOV_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mcomb, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, s, (double2*)w, N, (const double2*)V, vstride,
+                       nv, (const double2*)coef, sign, accumulate, norms ? partial : (double*)nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !norms) return e;
+    hipLaunchKernelGGL(k_partial_reduce, dim3(nrhs), dim3(256), 0, s, (const double*)partial, 1, norms);
+    return hipGetLastError();
+}
+
+hipError_t vec_norm2(const double* x, long long N, int nrhs, double* partial, double* norms, hipStream_t s) {
+    hipLaunchKernelGGL(k_vnorm2, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, s, (const double2*)x, N, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_partial_reduce, dim3(nrhs), dim3(256), 0, s, (const double*)partial, 1, norms);
+    return hipGetLastError();
+}
+
+hipError_t vec_scale(double* y, const double* x, long long N, int nrhs, const double* sc, hipStream_t s) {
+    hipLaunchKernelGGL(k_vscale, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, s, (double2*)y, (const double2*)x, N, sc);
     return hipGetLastError();
 }
 

@@ -38,12 +38,13 @@ def oracle_rhs_c0(n=16, N_t=16, T=1.0, p=1):
     return solvers.lift_constant(F, psi0, Mf, Ax)
 
 
+@pytest.mark.parametrize("refine", ["gmres", "plain"])
 @pytest.mark.parametrize("precision,tol", [(64, 1e-13), (32, 1e-12)])
-def test_c0_matches_dense_global_lu(precision, tol):
+def test_c0_matches_dense_global_lu(precision, tol, refine):
     nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(16, 16)
     F = oracle_rhs_c0()
     ref = solvers.solve_dense(Mt, Bt, Mx, Ax, F)
-    h = st.fdm_factor(Mt, Bt, Ms, As, 16, precision=precision, tol=tol, max_iter=40)
+    h = st.fdm_factor(Mt, Bt, Ms, As, 16, precision=precision, tol=tol, max_iter=40, refine=refine)
     Psi = to_host(h.solve(to_dev(F)))
     assert relerr(Psi, ref) < 1e-12 if precision == 64 else relerr(Psi, ref) < 1e-10
     assert solvers.relres(Mt, Bt, Mx, Ax, Psi, F) < max(tol, 1e-13) * 2
@@ -87,9 +88,10 @@ def test_adjoint_matches_dense(precision, tol):
     assert abs(np.vdot(G, x) - np.vdot(Lam, a)) < 1e-10 * abs(np.vdot(G, x))
 
 
-def test_no_convergence_is_reported():
+@pytest.mark.parametrize("refine", ["gmres", "plain"])
+def test_no_convergence_is_reported(refine):
     nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(16, 16)
-    h = st.fdm_factor(Mt, Bt, Ms, As, 16, precision=32, tol=1e-15, max_iter=0)
+    h = st.fdm_factor(Mt, Bt, Ms, As, 16, precision=32, tol=1e-15, max_iter=0, refine=refine)
     with pytest.raises(st.StfemError) as e:
         h.solve(to_dev(synth.random_rhs(1, 16, 225)))
     assert e.value.status == -5
@@ -120,8 +122,8 @@ def test_c2_fp32_refined_and_fp64_reach_1e10():
     nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(wl.n, wl.N_t, wl.T)
     F = synth.manufactured_rhs(wl)
     res = {}
-    for precision in (32, 64):
-        h = st.fdm_factor(Mt, Bt, Ms, As, wl.n, precision=precision, tol=1e-10, max_iter=60)
+    for precision, refine in ((32, "gmres"), (32, "plain"), (64, "gmres")):
+        h = st.fdm_factor(Mt, Bt, Ms, As, wl.n, precision=precision, tol=1e-10, max_iter=60, refine=refine)
         Psi = to_host(h.solve(to_dev(F)))
         res[precision] = (Psi, h.last_report)
         h.close()
@@ -131,3 +133,20 @@ def test_c2_fp32_refined_and_fp64_reach_1e10():
     # both precisions solve the same system
     assert relerr(res[32][0], res[64][0]) < 1e-7
     assert relerr(res[64][0], synth.manufactured_psi_hat(wl)) < 1e-2
+
+
+def test_gmres_restarts_and_multiple_rhs_converge():
+    """A Krylov space of 2 columns forces restarts; each rhs of a batch keeps
+    its own Hessenberg matrix, including a zero rhs (solution 0)."""
+    wl = synth.WORKLOADS["c0"]
+    nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(wl.n, wl.N_t, wl.T)
+    F = synth.random_rhs(5, wl.n_t, wl.n_x, 3)
+    F[1] = 0
+    F[2] *= 1e-6
+    h = st.fdm_factor(Mt, Bt, Ms, As, wl.n, precision=32, tol=1e-13, max_iter=30, restart=2)
+    Psi = to_host(h.solve(to_dev(F)))
+    assert h.last_report["rel_residual"] <= 1e-13
+    assert h.last_report["iterations"] >= 2         # at least one restart
+    assert np.all(Psi[1] == 0)
+    for r in (0, 2):
+        assert solvers.relres(Mt, Bt, Mx, Ax, Psi[r], F[r]) <= 2e-13
