@@ -441,32 +441,37 @@ constexpr int SWEEP_QL = 9;        // 16-byte units per producer thread and pane
 // One workgroup of 8 waves solves S_l x = g for NR right-hand sides:
 // L y = g, z = D^{-1} y, L^T x = z.  The sweeps walk the factor panel by
 // panel (NB columns); a panel, NB columns of band storage, is one contiguous
-// chunk of memory.  Waves 4-7 are producers: they stream panels from HBM into
-// a ring of three LDS slots, two panels ahead of their use, so their waits on
-// memory never stall the arithmetic.  Waves 0-3 are consumers; the rows a
-// panel touches (kd + NB) live in an LDS ring of Sz slots per rhs (Sz a power
-// of two >= kd + 2 NB).
-//  forward  consumer wave 0 solves the unit triangle of the diagonal block
-//           (register broadcasts between lanes), then every consumer thread
-//           updates one of the kd rows below;
-//  backward every consumer wave forms dot products of its panel columns with
-//           the finished x below (lanes over rows, wave reductions), then
-//           wave 0 solves the transposed diagonal triangle.
-// Each panel step has three workgroup barriers, all of them LDS-only: no wave
-// waits at a barrier for its own global loads.  A producer stores the panel
-// it loaded one step earlier and then issues the loads of the next one.
+// chunk of memory.  Waves 4-7 are producers: they store into a ring of three
+// LDS slots the panel they loaded one step earlier, then issue the loads of
+// the next one.  Waves 0-3 are consumers; the rows within reach of the
+// current panels live in an LDS ring of Sz slots per rhs (Sz a power of two
+// >= kd + 2 NB).  The consumers pipeline two panels, so that each panel step
+// needs a single LDS-only barrier (no wave waits there for global memory):
+//  forward, step p   wave 0 subtracts the contributions of panel p-1 from
+//                    the NB rows of panel p and solves their unit triangle
+//                    (register broadcasts between lanes); waves 1-3 subtract
+//                    the contributions of panel p-1 from the kd - NB rows
+//                    below panel p and fetch the NB rows of g that enter;
+//  backward, step b  (panel p = last - b) wave 0 forms the dot products of the
+//                    columns of panel p with the x of panel p+1, adds the far
+//                    sums prepared one step earlier and solves the transposed
+//                    triangle; waves 1-3 form the far sums of panel p-1 (dot
+//                    products with the x of panels >= p+1, lanes over rows).
+// This needs NB <= kd.
 template <class R, int NB, int NR, int KQ, bool CONJ>
 __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ band, Stencil st, const double* G,
                                                   double* U, long long rstride, int Sz) {
     typedef typename Unit<R>::T UT;
     constexpr int CPU = Unit<R>::CPU;
+    constexpr int CG = 64 / NB;              // lane groups of NB lanes in wave 0
+    constexpr int PER = (NB + CG - 1) / CG;  // columns (rows) per lane group
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int m = st.m, kd = st.n, n_x = m * m, ld = kd + 1;
     const int msk = Sz - 1;
     const int slot_units = (NB * ld + CPU - 1) / CPU;
     UT* ring = reinterpret_cast<UT*>(smem_raw);                       // 3 * slot_units
     cpx<R>* Y = reinterpret_cast<cpx<R>*>(ring + 3 * slot_units);      // Y[rh*Sz + slot]
-    cpx<R>* S = Y + NR * Sz;                                          // S[rh*NB + c]
+    cpx<R>* S2 = Y + NR * Sz;                                         // S2[par][rh*NB + c]
     const int l = blockIdx.x;
     const cpx<R>* Lb = band + (size_t)l * band_stride(st);
     const double2* g = reinterpret_cast<const double2*>(G) + (size_t)l * n_x;
@@ -474,11 +479,11 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool producer = wave >= 4;
     const int ptid = tid - 256;           // producer thread index
+    const int t1 = tid - 64;              // thread index within waves 1-3
     const int npanel = (n_x + NB - 1) / NB;
     const cpx<R> cz = {R(0), R(0)};
 
-    // ---- producers: panel p is loaded into registers one step before it is
-    // stored into its ring slot, so each load has a whole panel step to land
+    // ---- producers
     UT q[SWEEP_QL];
     auto pload = [&](int p) {
         p = min(max(p, 0), npanel - 1);
@@ -504,14 +509,23 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
         if (CONJ) v.y = -v.y;
         return v;
     };
+    auto lane_sum = [&](cpx<R> (&a)[NR], int from) {
+#pragma unroll
+        for (int off = from; off < 64; off <<= 1) {
+#pragma unroll
+            for (int rh = 0; rh < NR; ++rh) {
+                const cpx<R> o = shfl_xor(a[rh], off);
+                a[rh].x += o.x;
+                a[rh].y += o.y;
+            }
+        }
+    };
 
     // ===================================================== forward sweep
     if (producer) {
         pload(0);
         pstore(0, 0);
         pload(1);
-        if (npanel > 1) pstore(1, 1);
-        pload(2);
     } else {
         const int rows0 = min(NB + kd, n_x);
         for (int e = tid; e < NR * rows0; e += 256) {
@@ -522,57 +536,66 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
     }
     lds_barrier();
     for (int p = 0; p < npanel; ++p) {
-        const int slot = p % 3;
-        const int k = p * NB, nb = min(NB, n_x - k);
-        const int rh_in = min(tid / NB, NR - 1), i_in = k + NB + kd + (tid % NB);
-        const bool has_in = !producer && tid < NB * NR && i_in < n_x;
-        double2 gin = make_double2(0.0, 0.0);
-        // phase 1: triangle of the diagonal block
-        if (!producer) {
-            gin = g[(size_t)rh_in * rstride + min(i_in, n_x - 1)];
-            if (wave == 0) {
-                const int r = lane;
-                const int ys = (k + min(r, nb - 1)) & msk;
-                cpx<R> lrow[NB];                              // L[k+r][k+c], c < r
+        const int k = p * NB, nb = min(NB, n_x - k), kp = k - NB;
+        const int slot = p % 3, slotq = (p + 2) % 3;      // panels p and p-1
+        if (producer) {
+            if (p + 1 < npanel) pstore(p + 1, (p + 1) % 3);
+            pload(p + 2);
+        } else if (wave == 0) {
+            const int r = lane % NB, cg = lane / NB;
+            cpx<R> acc[NR];
 #pragma unroll
-                for (int c = 0; c < NB - 1; ++c) lrow[c] = (r > c && r < nb && r - c <= kd) ? PV(slot, c, r) : cz;
-                const cpx<R> dv = (r < nb) ? PV(slot, r, r) : cpx<R>{R(1), R(0)};
-                cpx<R> y[NR];
+            for (int rh = 0; rh < NR; ++rh) acc[rh] = cz;
+            if (p > 0) {
 #pragma unroll
-                for (int rh = 0; rh < NR; ++rh) y[rh] = Y[rh * Sz + ys];
+                for (int q2 = 0; q2 < PER; ++q2) {
+                    const int c = cg + CG * q2;
+                    if (c < NB && r < nb && NB + r - c <= kd) {
+                        const cpx<R> lv = PV(slotq, c, NB + r);
 #pragma unroll
-                for (int c = 0; c < NB - 1; ++c) {
-#pragma unroll
-                    for (int rh = 0; rh < NR; ++rh) y[rh] = csub(y[rh], cmul(lrow[c], rdlane(y[rh], c)));
-                }
-                if (r < nb) {
-                    bool ok;
-                    const cpx<R> dinv = cinv_or_zero(dv, ok);
-#pragma unroll
-                    for (int rh = 0; rh < NR; ++rh) {
-                        Y[rh * Sz + ys] = y[rh];
-                        const cpx<R> z = cmul(y[rh], dinv);
-                        u[(size_t)rh * rstride + k + r] = make_double2((double)z.x, (double)z.y);
+                        for (int rh = 0; rh < NR; ++rh) acc[rh] = cfma(lv, Y[rh * Sz + ((kp + c) & msk)], acc[rh]);
                     }
                 }
+                lane_sum(acc, NB);
             }
-        }
-        lds_barrier();
-        // phase 2: the kd rows below the panel
-        if (!producer) {
-            for (int t = tid; t < kd; t += 256) {
-                const int i = k + nb + t;
-                if (i < n_x) {
+            const int ys = (k + min(r, nb - 1)) & msk;
+            cpx<R> lrow[NB];                                  // L[k+r][k+c], c < r
+#pragma unroll
+            for (int c = 0; c < NB - 1; ++c) lrow[c] = (r > c && r < nb) ? PV(slot, c, r) : cz;
+            const cpx<R> dv = (r < nb) ? PV(slot, r, r) : cpx<R>{R(1), R(0)};
+            cpx<R> y[NR];
+#pragma unroll
+            for (int rh = 0; rh < NR; ++rh) y[rh] = csub(Y[rh * Sz + ys], acc[rh]);
+#pragma unroll
+            for (int c = 0; c < NB - 1; ++c) {
+#pragma unroll
+                for (int rh = 0; rh < NR; ++rh) y[rh] = csub(y[rh], cmul(lrow[c], rdlane(y[rh], c)));
+            }
+            if (lane < nb) {
+                bool ok;
+                const cpx<R> dinv = cinv_or_zero(dv, ok);
+#pragma unroll
+                for (int rh = 0; rh < NR; ++rh) {
+                    Y[rh * Sz + ys] = y[rh];
+                    const cpx<R> z = cmul(y[rh], dinv);
+                    u[(size_t)rh * rstride + k + lane] = make_double2((double)z.x, (double)z.y);
+                }
+            }
+        } else {
+            if (p > 0) {
+                const int ihi = min(k - 1 + kd, n_x - 1);
+                for (int i = k + NB + t1; i <= ihi; i += 192) {
+                    const int rr = i - kp;                    // row offset in panel p-1
                     cpx<R> acc[NR];
 #pragma unroll
                     for (int rh = 0; rh < NR; ++rh) acc[rh] = cz;
-                    const int c0 = nb + t - kd;               // columns whose band reaches row i
 #pragma unroll
                     for (int c = 0; c < NB; ++c) {
-                        if (c >= c0 && c < nb) {
-                            const cpx<R> lv = PV(slot, c, nb + t);
+                        if (rr - c <= kd) {
+                            const cpx<R> lv = PV(slotq, c, rr);
 #pragma unroll
-                            for (int rh = 0; rh < NR; ++rh) acc[rh] = cfma(lv, Y[rh * Sz + ((k + c) & msk)], acc[rh]);
+                            for (int rh = 0; rh < NR; ++rh)
+                                acc[rh] = cfma(lv, Y[rh * Sz + ((kp + c) & msk)], acc[rh]);
                         }
                     }
 #pragma unroll
@@ -582,97 +605,110 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
                     }
                 }
             }
-        }
-        lds_barrier();
-        // phase 3: producers fill the slot of panel p+2; rows entering the window
-        if (producer) {
-            if (p + 2 < npanel) pstore(p + 2, (p + 2) % 3);
-            pload(p + 3);
-        } else if (has_in) {
-            Y[rh_in * Sz + (i_in & msk)] = {(R)gin.x, (R)gin.y};
+            if (t1 < NB * NR) {                               // rows first reached at step p+1
+                const int rh = t1 / NB, i = k + kd + (t1 % NB);
+                if (i < n_x) {
+                    const double2 v = g[(size_t)rh * rstride + i];
+                    Y[rh * Sz + (i & msk)] = {(R)v.x, (R)v.y};
+                }
+            }
         }
         lds_barrier();
     }
 
     // ==================================================== backward sweep
-    // panel p = npanel-1-b is consumed at backward step b from slot b % 3
+    // step b works on panel p = npanel-1-b (slot b % 3) and panel p-1 (slot
+    // (b+1) % 3); the far sums of panel p are in S2[b & 1]
+    cpx<R> zc[NR];
     if (producer) {
         pload(npanel - 1);
         pstore(npanel - 1, 0);
         pload(npanel - 2);
         if (npanel > 1) pstore(npanel - 2, 1);
         pload(npanel - 3);
+    } else if (wave == 0) {
+        const int k = (npanel - 1) * NB;
+#pragma unroll
+        for (int rh = 0; rh < NR; ++rh) {
+            const double2 z = u[(size_t)rh * rstride + min(k + (lane % NB), n_x - 1)];
+            zc[rh] = {(R)z.x, (R)z.y};
+        }
+    } else if (t1 < NR * NB) {
+        S2[t1] = cz;
     }
     lds_barrier();
     for (int b = 0; b < npanel; ++b) {
-        const int slot = b % 3;
         const int p = npanel - 1 - b;
-        const int k = p * NB, nb = min(NB, n_x - k);
-        // phase 1: dot products of the panel columns with the finished x below
-        cpx<R> zc[NR];
-        if (!producer) {
-            if (wave == 0) {
+        const int k = p * NB, nb = min(NB, n_x - k), kp = k - NB;
+        const int slot = b % 3, slotq = (b + 1) % 3;      // panels p and p-1
+        const cpx<R>* S2r = S2 + (b & 1) * NR * NB;
+        cpx<R>* S2w = S2 + ((b + 1) & 1) * NR * NB;
+        if (producer) {
+            if (b + 2 < npanel) pstore(npanel - 3 - b, (b + 2) % 3);
+            pload(npanel - 4 - b);
+        } else if (wave == 0) {
+            const int c = lane % NB, rg = lane / NB;
+            cpx<R> acc[NR];
+#pragma unroll
+            for (int rh = 0; rh < NR; ++rh) acc[rh] = cz;
+#pragma unroll
+            for (int q2 = 0; q2 < PER; ++q2) {                // rows of panel p+1
+                const int j = rg + CG * q2, i = k + NB + j;
+                if (j < NB && i < n_x && c < nb && NB + j - c <= kd) {
+                    const cpx<R> lv = PV(slot, c, NB + j);
+#pragma unroll
+                    for (int rh = 0; rh < NR; ++rh) acc[rh] = cfma(lv, Y[rh * Sz + (i & msk)], acc[rh]);
+                }
+            }
+            lane_sum(acc, NB);
+            const int r = c;
+            cpx<R> lcol[NB];                                  // L[k+cc][k+r], cc > r
+#pragma unroll
+            for (int cc = 1; cc < NB; ++cc) lcol[cc] = (r < cc && cc < nb) ? PV(slot, r, cc) : cz;
+            cpx<R> v[NR];
+#pragma unroll
+            for (int rh = 0; rh < NR; ++rh) v[rh] = (r < nb) ? csub(csub(zc[rh], S2r[rh * NB + r]), acc[rh]) : cz;
+#pragma unroll
+            for (int cc = NB - 1; cc >= 1; --cc) {
+#pragma unroll
+                for (int rh = 0; rh < NR; ++rh) v[rh] = csub(v[rh], cmul(lcol[cc], rdlane(v[rh], cc)));
+            }
+            if (lane < nb) {
 #pragma unroll
                 for (int rh = 0; rh < NR; ++rh) {
-                    const double2 z = u[(size_t)rh * rstride + min(k + lane, n_x - 1)];
+                    Y[rh * Sz + ((k + lane) & msk)] = v[rh];
+                    u[(size_t)rh * rstride + k + lane] = make_double2((double)v[rh].x, (double)v[rh].y);
+                }
+            }
+            if (p > 0) {                                      // z of panel p-1 for the next step
+#pragma unroll
+                for (int rh = 0; rh < NR; ++rh) {
+                    const double2 z = u[(size_t)rh * rstride + kp + (lane % NB)];
                     zc[rh] = {(R)z.x, (R)z.y};
                 }
             }
-            for (int c = wave; c < nb; c += 4) {
-                const int ilast = min(k + c + kd, n_x - 1);
+        } else if (p > 0) {
+            // far sums of panel p-1: rows k+NB .. kp+c+kd (x of panels >= p+1)
+            for (int c = wave - 1; c < NB; c += 3) {
+                const int ilast = min(kp + c + kd, n_x - 1);
                 cpx<R> part[NR];
 #pragma unroll
                 for (int rh = 0; rh < NR; ++rh) part[rh] = cz;
 #pragma unroll
                 for (int pq = 0; pq < 4 * KQ; ++pq) {
-                    const int i = k + nb + lane + 64 * pq;
+                    const int i = k + NB + lane + 64 * pq;
                     if (i <= ilast) {
-                        const cpx<R> lv = PV(slot, c, i - k);
+                        const cpx<R> lv = PV(slotq, c, i - kp);
 #pragma unroll
                         for (int rh = 0; rh < NR; ++rh) part[rh] = cfma(lv, Y[rh * Sz + (i & msk)], part[rh]);
                     }
                 }
+                lane_sum(part, 1);
+                if (lane == 0) {
 #pragma unroll
-                for (int rh = 0; rh < NR; ++rh) {
-                    cpx<R> v = part[rh];
-#pragma unroll
-                    for (int off = 32; off >= 1; off >>= 1) {
-                        const cpx<R> o = shfl_xor(v, off);
-                        v.x += o.x;
-                        v.y += o.y;
-                    }
-                    if (lane == 0) S[rh * NB + c] = v;
+                    for (int rh = 0; rh < NR; ++rh) S2w[rh * NB + c] = part[rh];
                 }
             }
-        }
-        lds_barrier();
-        // phase 2: transposed triangle of the diagonal block
-        if (!producer && wave == 0) {
-            const int r = lane;
-            cpx<R> lcol[NB];                                  // L[k+c][k+r], c > r
-#pragma unroll
-            for (int c = 1; c < NB; ++c) lcol[c] = (r < c && c < nb && c - r <= kd) ? PV(slot, r, c) : cz;
-            cpx<R> v[NR];
-#pragma unroll
-            for (int rh = 0; rh < NR; ++rh) v[rh] = (r < nb) ? csub(zc[rh], S[rh * NB + r]) : cz;
-#pragma unroll
-            for (int c = NB - 1; c >= 1; --c) {
-#pragma unroll
-                for (int rh = 0; rh < NR; ++rh) v[rh] = csub(v[rh], cmul(lcol[c], rdlane(v[rh], c)));
-            }
-            if (r < nb) {
-#pragma unroll
-                for (int rh = 0; rh < NR; ++rh) {
-                    Y[rh * Sz + ((k + r) & msk)] = v[rh];
-                    u[(size_t)rh * rstride + k + r] = make_double2((double)v[rh].x, (double)v[rh].y);
-                }
-            }
-        }
-        lds_barrier();
-        // phase 3: producers fill the slot of backward step b+2
-        if (producer) {
-            if (b + 2 < npanel) pstore(npanel - 3 - b, (b + 2) % 3);
-            pload(npanel - 4 - b);
         }
         lds_barrier();
     }
@@ -1028,7 +1064,7 @@ hipError_t launch_sweep_nr(const void* band, int count, const Stencil& st, const
     while (Sz < st.n + 2 * NB) Sz <<= 1;
     constexpr int CPU = Unit<R>::CPU;
     const size_t slot = (size_t)(NB * (st.n + 1) + CPU - 1) / CPU;   // 16-byte units
-    const size_t lds = 3 * slot * 16 + (NR * Sz + NR * NB) * sizeof(cpx<R>);
+    const size_t lds = 3 * slot * 16 + (NR * Sz + 2 * NR * NB) * sizeof(cpx<R>);
     if ((size_t)NB * (st.n + 1) > (size_t)SWEEP_QL * 256 * CPU) return hipErrorInvalidValue;
     if (conj) {
         auto kern = k_sweep<R, NB, NR, KQ, true>;
@@ -1070,16 +1106,19 @@ hipError_t launch_sweep_nb(const void* band, int count, const Stencil& st, const
     return hipSuccess;
 }
 
-// Panel width of the sweeps: the widest of 16, 8, 4 columns whose panel
-// (NB (kd + 1) complex values) fits the SWEEP_QL 16-byte loads per thread.
+// Panel width of the sweeps: the widest of 16, 8, 4, 2 columns that is at
+// most kd and whose panel (NB (kd + 1) complex values) fits the SWEEP_QL
+// 16-byte loads per thread.
 template <class R, int KQ>
 hipError_t launch_sweep_kq(const void* band, int count, const Stencil& st, const double* G, double* U, int nrhs,
                            int conj, hipStream_t s) {
     const size_t cap = (size_t)SWEEP_QL * 256 * Unit<R>::CPU;
     const size_t ld = st.n + 1;
-    if (16 * ld <= cap) return launch_sweep_nb<R, 16, KQ>(band, count, st, G, U, nrhs, conj, s);
-    if (8 * ld <= cap) return launch_sweep_nb<R, 8, KQ>(band, count, st, G, U, nrhs, conj, s);
-    if (4 * ld <= cap) return launch_sweep_nb<R, 4, KQ>(band, count, st, G, U, nrhs, conj, s);
+    const int kd = st.n;
+    if (16 <= kd && 16 * ld <= cap) return launch_sweep_nb<R, 16, KQ>(band, count, st, G, U, nrhs, conj, s);
+    if (8 <= kd && 8 * ld <= cap) return launch_sweep_nb<R, 8, KQ>(band, count, st, G, U, nrhs, conj, s);
+    if (4 <= kd && 4 * ld <= cap) return launch_sweep_nb<R, 4, KQ>(band, count, st, G, U, nrhs, conj, s);
+    if (2 <= kd && 2 * ld <= cap) return launch_sweep_nb<R, 2, KQ>(band, count, st, G, U, nrhs, conj, s);
     return hipErrorInvalidValue;
 }
 
