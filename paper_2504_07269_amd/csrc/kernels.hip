@@ -58,6 +58,44 @@ __device__ __forceinline__ cpx<R> shfl_xor(cpx<R> v, int mask) {
     return {__shfl_xor(v.x, mask, 64), __shfl_xor(v.y, mask, 64)};
 }
 
+// Lane permutations by DPP (a VALU operand modifier, no LDS round trip):
+// quad_perm [1,0,3,2] and [2,3,0,1] (partner lane ^1, ^2), half-row mirror
+// (lane i <-> 7-i within 8) and row mirror (i <-> 15-i within 16).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL, class R>
+__device__ __forceinline__ void add_dpp(cpx<R>& a) {
+    a.x += dpp<CTRL>(a.x);
+    a.y += dpp<CTRL>(a.y);
+}
+// Sum over aligned groups of G consecutive lanes; every lane of a group
+// receives the group's total.
+template <int G, class R>
+__device__ __forceinline__ void group_sum(cpx<R>& a) {
+    if (G >= 2) add_dpp<0xB1>(a);
+    if (G >= 4) add_dpp<0x4E>(a);
+    if (G >= 8) add_dpp<0x141>(a);
+    if (G >= 16) add_dpp<0x140>(a);
+    if (G >= 32) {
+        const cpx<R> o = shfl_xor(a, 16);
+        a.x += o.x;
+        a.y += o.y;
+    }
+    if (G >= 64) {
+        const cpx<R> o = shfl_xor(a, 32);
+        a.x += o.x;
+        a.y += o.y;
+    }
+}
+
 // Complex values between consecutive blocks of band storage: n_x (kd + 1)
 // rounded up to a multiple of 64, so that every block starts 512-byte aligned.
 __host__ __device__ __forceinline__ long long band_stride(const Stencil& st) {
@@ -455,23 +493,28 @@ constexpr int SWEEP_QL = 9;        // 16-byte units per producer thread and pane
 //  backward, step b  (panel p = last - b) wave 0 forms the dot products of the
 //                    columns of panel p with the x of panel p+1, adds the far
 //                    sums prepared one step earlier and solves the transposed
-//                    triangle; waves 1-3 form the far sums of panel p-1 (dot
-//                    products with the x of panels >= p+1, lanes over rows).
-// This needs NB <= kd.
-template <class R, int NB, int NR, int KQ, bool CONJ>
+//                    triangle; waves 1-3 form the far sums of panel p-1: the
+//                    dot products of its columns with the x of panels >= p+1,
+//                    RL = 192/NB threads per column, whose partial sums wave 0
+//                    adds up.  Each thread's rows are rotated by its column,
+//                    so that the lanes of one LDS read hit distinct banks.
+// In wave 0 a row (or column) of the panel is owned by a group of CG = 64/NB
+// consecutive lanes; group sums use DPP lane permutations.  Needs NB <= kd.
+template <class R, int NB, int NR, bool CONJ>
 __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ band, Stencil st, const double* G,
                                                   double* U, long long rstride, int Sz) {
     typedef typename Unit<R>::T UT;
     constexpr int CPU = Unit<R>::CPU;
-    constexpr int CG = 64 / NB;              // lane groups of NB lanes in wave 0
-    constexpr int PER = (NB + CG - 1) / CG;  // columns (rows) per lane group
+    constexpr int CG = 64 / NB;              // lanes per row (column) in wave 0
+    constexpr int PER = (NB + CG - 1) / CG;  // columns (rows) per lane of a group
+    constexpr int RL = 192 / NB;             // threads per column in the far sums
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int m = st.m, kd = st.n, n_x = m * m, ld = kd + 1;
     const int msk = Sz - 1;
     const int slot_units = (NB * ld + CPU - 1) / CPU;
     UT* ring = reinterpret_cast<UT*>(smem_raw);                       // 3 * slot_units
     cpx<R>* Y = reinterpret_cast<cpx<R>*>(ring + 3 * slot_units);      // Y[rh*Sz + slot]
-    cpx<R>* S2 = Y + NR * Sz;                                         // S2[par][rh*NB + c]
+    cpx<R>* P = Y + NR * Sz;                                          // P[par][(t*NR + rh)*NB + c]
     const int l = blockIdx.x;
     const cpx<R>* Lb = band + (size_t)l * band_stride(st);
     const double2* g = reinterpret_cast<const double2*>(G) + (size_t)l * n_x;
@@ -509,17 +552,6 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
         if (CONJ) v.y = -v.y;
         return v;
     };
-    auto lane_sum = [&](cpx<R> (&a)[NR], int from) {
-#pragma unroll
-        for (int off = from; off < 64; off <<= 1) {
-#pragma unroll
-            for (int rh = 0; rh < NR; ++rh) {
-                const cpx<R> o = shfl_xor(a[rh], off);
-                a[rh].x += o.x;
-                a[rh].y += o.y;
-            }
-        }
-    };
 
     // ===================================================== forward sweep
     if (producer) {
@@ -542,7 +574,7 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
             if (p + 1 < npanel) pstore(p + 1, (p + 1) % 3);
             pload(p + 2);
         } else if (wave == 0) {
-            const int r = lane % NB, cg = lane / NB;
+            const int r = lane / CG, cg = lane % CG;
             cpx<R> acc[NR];
 #pragma unroll
             for (int rh = 0; rh < NR; ++rh) acc[rh] = cz;
@@ -556,7 +588,8 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
                         for (int rh = 0; rh < NR; ++rh) acc[rh] = cfma(lv, Y[rh * Sz + ((kp + c) & msk)], acc[rh]);
                     }
                 }
-                lane_sum(acc, NB);
+#pragma unroll
+                for (int rh = 0; rh < NR; ++rh) group_sum<CG>(acc[rh]);
             }
             const int ys = (k + min(r, nb - 1)) & msk;
             cpx<R> lrow[NB];                                  // L[k+r][k+c], c < r
@@ -569,39 +602,54 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
 #pragma unroll
             for (int c = 0; c < NB - 1; ++c) {
 #pragma unroll
-                for (int rh = 0; rh < NR; ++rh) y[rh] = csub(y[rh], cmul(lrow[c], rdlane(y[rh], c)));
+                for (int rh = 0; rh < NR; ++rh) y[rh] = csub(y[rh], cmul(lrow[c], rdlane(y[rh], c * CG)));
             }
-            if (lane < nb) {
+            if (cg == 0 && r < nb) {
                 bool ok;
                 const cpx<R> dinv = cinv_or_zero(dv, ok);
 #pragma unroll
                 for (int rh = 0; rh < NR; ++rh) {
                     Y[rh * Sz + ys] = y[rh];
                     const cpx<R> z = cmul(y[rh], dinv);
-                    u[(size_t)rh * rstride + k + lane] = make_double2((double)z.x, (double)z.y);
+                    u[(size_t)rh * rstride + k + r] = make_double2((double)z.x, (double)z.y);
                 }
             }
         } else {
             if (p > 0) {
                 const int ihi = min(k - 1 + kd, n_x - 1);
-                for (int i = k + NB + t1; i <= ihi; i += 192) {
-                    const int rr = i - kp;                    // row offset in panel p-1
-                    cpx<R> acc[NR];
+                if constexpr (NR == 1) {
+                    cpx<R> yq[NB];                            // y of panel p-1
 #pragma unroll
-                    for (int rh = 0; rh < NR; ++rh) acc[rh] = cz;
+                    for (int c = 0; c < NB; ++c) yq[c] = Y[(kp + c) & msk];
+                    for (int i = k + NB + t1; i <= ihi; i += 192) {
+                        const int rr = i - kp;                // row offset in panel p-1
+                        cpx<R> acc = cz;
 #pragma unroll
-                    for (int c = 0; c < NB; ++c) {
-                        if (rr - c <= kd) {
-                            const cpx<R> lv = PV(slotq, c, rr);
-#pragma unroll
-                            for (int rh = 0; rh < NR; ++rh)
-                                acc[rh] = cfma(lv, Y[rh * Sz + ((kp + c) & msk)], acc[rh]);
-                        }
+                        for (int c = 0; c < NB; ++c)
+                            if (rr - c <= kd) acc = cfma(PV(slotq, c, rr), yq[c], acc);
+                        cpx<R>& yi = Y[i & msk];
+                        yi = csub(yi, acc);
                     }
+                } else {
+                    for (int i = k + NB + t1; i <= ihi; i += 192) {
+                        const int rr = i - kp;
+                        cpx<R> acc[NR];
 #pragma unroll
-                    for (int rh = 0; rh < NR; ++rh) {
-                        cpx<R>& yi = Y[rh * Sz + (i & msk)];
-                        yi = csub(yi, acc[rh]);
+                        for (int rh = 0; rh < NR; ++rh) acc[rh] = cz;
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) {
+                            if (rr - c <= kd) {
+                                const cpx<R> lv = PV(slotq, c, rr);
+#pragma unroll
+                                for (int rh = 0; rh < NR; ++rh)
+                                    acc[rh] = cfma(lv, Y[rh * Sz + ((kp + c) & msk)], acc[rh]);
+                            }
+                        }
+#pragma unroll
+                        for (int rh = 0; rh < NR; ++rh) {
+                            cpx<R>& yi = Y[rh * Sz + (i & msk)];
+                            yi = csub(yi, acc[rh]);
+                        }
                     }
                 }
             }
@@ -618,7 +666,8 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
 
     // ==================================================== backward sweep
     // step b works on panel p = npanel-1-b (slot b % 3) and panel p-1 (slot
-    // (b+1) % 3); the far sums of panel p are in S2[b & 1]
+    // (b+1) % 3); the partial far sums of panel p are in P[b & 1]
+    const int far_period = (kd - NB + RL - 1) / RL * RL;  // >= rows of the longest column
     cpx<R> zc[NR];
     if (producer) {
         pload(npanel - 1);
@@ -630,24 +679,24 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
         const int k = (npanel - 1) * NB;
 #pragma unroll
         for (int rh = 0; rh < NR; ++rh) {
-            const double2 z = u[(size_t)rh * rstride + min(k + (lane % NB), n_x - 1)];
+            const double2 z = u[(size_t)rh * rstride + min(k + lane / CG, n_x - 1)];
             zc[rh] = {(R)z.x, (R)z.y};
         }
-    } else if (t1 < NR * NB) {
-        S2[t1] = cz;
+    } else {
+        for (int e = t1; e < RL * NR * NB; e += 192) P[e] = cz;
     }
     lds_barrier();
     for (int b = 0; b < npanel; ++b) {
         const int p = npanel - 1 - b;
         const int k = p * NB, nb = min(NB, n_x - k), kp = k - NB;
         const int slot = b % 3, slotq = (b + 1) % 3;      // panels p and p-1
-        const cpx<R>* S2r = S2 + (b & 1) * NR * NB;
-        cpx<R>* S2w = S2 + ((b + 1) & 1) * NR * NB;
+        const cpx<R>* Pr = P + (b & 1) * RL * NR * NB;
+        cpx<R>* Pw = P + ((b + 1) & 1) * RL * NR * NB;
         if (producer) {
             if (b + 2 < npanel) pstore(npanel - 3 - b, (b + 2) % 3);
             pload(npanel - 4 - b);
         } else if (wave == 0) {
-            const int c = lane % NB, rg = lane / NB;
+            const int c = lane / CG, rg = lane % CG;
             cpx<R> acc[NR];
 #pragma unroll
             for (int rh = 0; rh < NR; ++rh) acc[rh] = cz;
@@ -660,55 +709,63 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
                     for (int rh = 0; rh < NR; ++rh) acc[rh] = cfma(lv, Y[rh * Sz + (i & msk)], acc[rh]);
                 }
             }
-            lane_sum(acc, NB);
+#pragma unroll
+            for (int rh = 0; rh < NR; ++rh) {
+                group_sum<CG>(acc[rh]);
+#pragma unroll 4
+                for (int t = 0; t < RL; ++t) {                // far sums
+                    const cpx<R> f = Pr[(t * NR + rh) * NB + c];
+                    acc[rh].x += f.x;
+                    acc[rh].y += f.y;
+                }
+            }
             const int r = c;
             cpx<R> lcol[NB];                                  // L[k+cc][k+r], cc > r
 #pragma unroll
             for (int cc = 1; cc < NB; ++cc) lcol[cc] = (r < cc && cc < nb) ? PV(slot, r, cc) : cz;
             cpx<R> v[NR];
 #pragma unroll
-            for (int rh = 0; rh < NR; ++rh) v[rh] = (r < nb) ? csub(csub(zc[rh], S2r[rh * NB + r]), acc[rh]) : cz;
+            for (int rh = 0; rh < NR; ++rh) v[rh] = (r < nb) ? csub(zc[rh], acc[rh]) : cz;
 #pragma unroll
             for (int cc = NB - 1; cc >= 1; --cc) {
 #pragma unroll
-                for (int rh = 0; rh < NR; ++rh) v[rh] = csub(v[rh], cmul(lcol[cc], rdlane(v[rh], cc)));
+                for (int rh = 0; rh < NR; ++rh) v[rh] = csub(v[rh], cmul(lcol[cc], rdlane(v[rh], cc * CG)));
             }
-            if (lane < nb) {
+            if (rg == 0 && r < nb) {
 #pragma unroll
                 for (int rh = 0; rh < NR; ++rh) {
-                    Y[rh * Sz + ((k + lane) & msk)] = v[rh];
-                    u[(size_t)rh * rstride + k + lane] = make_double2((double)v[rh].x, (double)v[rh].y);
+                    Y[rh * Sz + ((k + r) & msk)] = v[rh];
+                    u[(size_t)rh * rstride + k + r] = make_double2((double)v[rh].x, (double)v[rh].y);
                 }
             }
             if (p > 0) {                                      // z of panel p-1 for the next step
 #pragma unroll
                 for (int rh = 0; rh < NR; ++rh) {
-                    const double2 z = u[(size_t)rh * rstride + kp + (lane % NB)];
+                    const double2 z = u[(size_t)rh * rstride + kp + c];
                     zc[rh] = {(R)z.x, (R)z.y};
                 }
             }
         } else if (p > 0) {
-            // far sums of panel p-1: rows k+NB .. kp+c+kd (x of panels >= p+1)
-            for (int c = wave - 1; c < NB; c += 3) {
-                const int ilast = min(kp + c + kd, n_x - 1);
-                cpx<R> part[NR];
+            // partial far sums of panel p-1: column c, rows k+NB+j for j = rl,
+            // rl+RL, ... (rotated by c modulo far_period), j <= c + kd - 2 NB
+            const int c = t1 % NB, rl = t1 / NB;
+            const int ilast = min(kp + c + kd, n_x - 1);
+            cpx<R> part[NR];
 #pragma unroll
-                for (int rh = 0; rh < NR; ++rh) part[rh] = cz;
+            for (int rh = 0; rh < NR; ++rh) part[rh] = cz;
+            int j = far_period > 0 ? (rl + c) % far_period : 0;
+            for (int j0 = rl; j0 < far_period; j0 += RL) {
+                const int i = k + NB + j;
+                if (i <= ilast) {
+                    const cpx<R> lv = PV(slotq, c, i - kp);
 #pragma unroll
-                for (int pq = 0; pq < 4 * KQ; ++pq) {
-                    const int i = k + NB + lane + 64 * pq;
-                    if (i <= ilast) {
-                        const cpx<R> lv = PV(slotq, c, i - kp);
-#pragma unroll
-                        for (int rh = 0; rh < NR; ++rh) part[rh] = cfma(lv, Y[rh * Sz + (i & msk)], part[rh]);
-                    }
+                    for (int rh = 0; rh < NR; ++rh) part[rh] = cfma(lv, Y[rh * Sz + (i & msk)], part[rh]);
                 }
-                lane_sum(part, 1);
-                if (lane == 0) {
-#pragma unroll
-                    for (int rh = 0; rh < NR; ++rh) S2w[rh * NB + c] = part[rh];
-                }
+                j += RL;
+                if (j >= far_period) j -= far_period;
             }
+#pragma unroll
+            for (int rh = 0; rh < NR; ++rh) Pw[(rl * NR + rh) * NB + c] = part[rh];
         }
         lds_barrier();
     }
@@ -1057,48 +1114,54 @@ hipError_t launch_ldlt(void* band, int count, const Stencil& st, int* info, hipS
     return hipGetLastError();
 }
 
-template <class R, int NB, int NR, int KQ>
+// Dynamic LDS of k_sweep: three panel slots, the Y ring, the far-sum partials.
+template <class R, int NB, int NR>
+size_t sweep_lds_bytes(int kd, int& Sz) {
+    Sz = 1;
+    while (Sz < kd + 2 * NB) Sz <<= 1;
+    constexpr int CPU = Unit<R>::CPU;
+    const size_t slot = (size_t)(NB * (kd + 1) + CPU - 1) / CPU;   // 16-byte units
+    return 3 * slot * 16 + ((size_t)NR * Sz + 2 * (size_t)(192 / NB) * NR * NB) * sizeof(cpx<R>);
+}
+constexpr size_t SWEEP_LDS_CAP = 160u * 1024u;
+
+template <class R, int NB, int NR>
 hipError_t launch_sweep_nr(const void* band, int count, const Stencil& st, const double* G, double* U, int conj,
                            long long rstride, hipStream_t s) {
-    int Sz = 1;
-    while (Sz < st.n + 2 * NB) Sz <<= 1;
-    constexpr int CPU = Unit<R>::CPU;
-    const size_t slot = (size_t)(NB * (st.n + 1) + CPU - 1) / CPU;   // 16-byte units
-    const size_t lds = 3 * slot * 16 + (NR * Sz + 2 * NR * NB) * sizeof(cpx<R>);
-    if ((size_t)NB * (st.n + 1) > (size_t)SWEEP_QL * 256 * CPU) return hipErrorInvalidValue;
-    if (conj) {
-        auto kern = k_sweep<R, NB, NR, KQ, true>;
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(count), dim3(512), lds, s, (const cpx<R>*)band, st, G, U, rstride, Sz);
-    } else {
-        auto kern = k_sweep<R, NB, NR, KQ, false>;
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(count), dim3(512), lds, s, (const cpx<R>*)band, st, G, U, rstride, Sz);
-    }
+    int Sz = 0;
+    const size_t lds = sweep_lds_bytes<R, NB, NR>(st.n, Sz);
+    if ((size_t)NB * (st.n + 1) > (size_t)SWEEP_QL * 256 * Unit<R>::CPU || lds > SWEEP_LDS_CAP)
+        return hipErrorInvalidValue;
+    auto kern = conj ? k_sweep<R, NB, NR, true> : k_sweep<R, NB, NR, false>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(count), dim3(512), lds, s, (const cpx<R>*)band, st, G, U, rstride, Sz);
     return hipGetLastError();
 }
 
-// Right-hand sides go through the kernel 4, then 2, then 1 at a time.
-template <class R, int NB, int KQ>
+// Right-hand sides go through the kernel 4, then 2, then 1 at a time (fewer
+// at once where the LDS of 4 or 2 would not fit).
+template <class R, int NB>
 hipError_t launch_sweep_nb(const void* band, int count, const Stencil& st, const double* G, double* U, int nrhs,
                            int conj, hipStream_t s) {
     const long long rstride = (long long)count * st.m * st.m;   // complex elements between rhs
+    int Sz = 0;
+    const bool fit4 = sweep_lds_bytes<R, NB, 4>(st.n, Sz) <= SWEEP_LDS_CAP;
+    const bool fit2 = sweep_lds_bytes<R, NB, 2>(st.n, Sz) <= SWEEP_LDS_CAP;
     int r0 = 0;
     while (r0 < nrhs) {
         const int left = nrhs - r0;
         const double* Gr = G + (size_t)r0 * rstride * 2;
         double* Ur = U + (size_t)r0 * rstride * 2;
         hipError_t e;
-        if (left >= 4) {
-            e = launch_sweep_nr<R, NB, 4, KQ>(band, count, st, Gr, Ur, conj, rstride, s);
+        if (left >= 4 && fit4) {
+            e = launch_sweep_nr<R, NB, 4>(band, count, st, Gr, Ur, conj, rstride, s);
             r0 += 4;
-        } else if (left >= 2) {
-            e = launch_sweep_nr<R, NB, 2, KQ>(band, count, st, Gr, Ur, conj, rstride, s);
+        } else if (left >= 2 && fit2) {
+            e = launch_sweep_nr<R, NB, 2>(band, count, st, Gr, Ur, conj, rstride, s);
             r0 += 2;
         } else {
-            e = launch_sweep_nr<R, NB, 1, KQ>(band, count, st, Gr, Ur, conj, rstride, s);
+            e = launch_sweep_nr<R, NB, 1>(band, count, st, Gr, Ur, conj, rstride, s);
             r0 += 1;
         }
         if (e != hipSuccess) return e;
@@ -1109,25 +1172,16 @@ hipError_t launch_sweep_nb(const void* band, int count, const Stencil& st, const
 // Panel width of the sweeps: the widest of 16, 8, 4, 2 columns that is at
 // most kd and whose panel (NB (kd + 1) complex values) fits the SWEEP_QL
 // 16-byte loads per thread.
-template <class R, int KQ>
-hipError_t launch_sweep_kq(const void* band, int count, const Stencil& st, const double* G, double* U, int nrhs,
-                           int conj, hipStream_t s) {
-    const size_t cap = (size_t)SWEEP_QL * 256 * Unit<R>::CPU;
-    const size_t ld = st.n + 1;
-    const int kd = st.n;
-    if (16 <= kd && 16 * ld <= cap) return launch_sweep_nb<R, 16, KQ>(band, count, st, G, U, nrhs, conj, s);
-    if (8 <= kd && 8 * ld <= cap) return launch_sweep_nb<R, 8, KQ>(band, count, st, G, U, nrhs, conj, s);
-    if (4 <= kd && 4 * ld <= cap) return launch_sweep_nb<R, 4, KQ>(band, count, st, G, U, nrhs, conj, s);
-    if (2 <= kd && 2 * ld <= cap) return launch_sweep_nb<R, 2, KQ>(band, count, st, G, U, nrhs, conj, s);
-    return hipErrorInvalidValue;
-}
-
 template <class R>
 hipError_t launch_sweep(const void* band, int count, const Stencil& st, const double* G, double* U, int nrhs, int conj,
                         hipStream_t s) {
-    if (st.n <= 256) return launch_sweep_kq<R, 1>(band, count, st, G, U, nrhs, conj, s);
-    if (st.n <= 512) return launch_sweep_kq<R, 2>(band, count, st, G, U, nrhs, conj, s);
-    if (st.n <= 1024) return launch_sweep_kq<R, 4>(band, count, st, G, U, nrhs, conj, s);
+    const size_t cap = (size_t)SWEEP_QL * 256 * Unit<R>::CPU;
+    const size_t ld = st.n + 1;
+    const int kd = st.n;
+    if (16 <= kd && 16 * ld <= cap) return launch_sweep_nb<R, 16>(band, count, st, G, U, nrhs, conj, s);
+    if (8 <= kd && 8 * ld <= cap) return launch_sweep_nb<R, 8>(band, count, st, G, U, nrhs, conj, s);
+    if (4 <= kd && 4 * ld <= cap) return launch_sweep_nb<R, 4>(band, count, st, G, U, nrhs, conj, s);
+    if (2 <= kd && 2 * ld <= cap) return launch_sweep_nb<R, 2>(band, count, st, G, U, nrhs, conj, s);
     return hipErrorInvalidValue;
 }
 
