@@ -474,28 +474,30 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
 }
 
 // ---------------------------------------------------------------------- sweeps
-constexpr int SWEEP_QL = 9;        // 16-byte units per producer thread and panel
+constexpr int SWEEP_QL = 11;       // 16-byte units per producer thread and panel
+constexpr int SWEEP_BULK = 256;    // threads of waves 1-4
+constexpr int SWEEP_PROD = 192;    // threads of waves 5-7
 
 // One workgroup of 8 waves solves S_l x = g for NR right-hand sides:
 // L y = g, z = D^{-1} y, L^T x = z.  The sweeps walk the factor panel by
 // panel (NB columns); a panel, NB columns of band storage, is one contiguous
-// chunk of memory.  Waves 4-7 are producers: they store into a ring of three
+// chunk of memory.  Waves 5-7 are producers: they store into a ring of three
 // LDS slots the panel they loaded one step earlier, then issue the loads of
-// the next one.  Waves 0-3 are consumers; the rows within reach of the
+// the next one.  Waves 0-4 are consumers; the rows within reach of the
 // current panels live in an LDS ring of Sz slots per rhs (Sz a power of two
 // >= kd + 2 NB).  The consumers pipeline two panels, so that each panel step
 // needs a single LDS-only barrier (no wave waits there for global memory):
 //  forward, step p   wave 0 subtracts the contributions of panel p-1 from
 //                    the NB rows of panel p and solves their unit triangle
-//                    (register broadcasts between lanes); waves 1-3 subtract
+//                    (register broadcasts between lanes); waves 1-4 subtract
 //                    the contributions of panel p-1 from the kd - NB rows
 //                    below panel p and fetch the NB rows of g that enter;
 //  backward, step b  (panel p = last - b) wave 0 forms the dot products of the
 //                    columns of panel p with the x of panel p+1, adds the far
 //                    sums prepared one step earlier and solves the transposed
-//                    triangle; waves 1-3 form the far sums of panel p-1: the
+//                    triangle; waves 1-4 form the far sums of panel p-1: the
 //                    dot products of its columns with the x of panels >= p+1,
-//                    RL = 192/NB threads per column, whose partial sums wave 0
+//                    RL = 256/NB threads per column, whose partial sums wave 0
 //                    adds up.  Each thread's rows are rotated by its column,
 //                    so that the lanes of one LDS read hit distinct banks.
 // In wave 0 a row (or column) of the panel is owned by a group of CG = 64/NB
@@ -507,7 +509,7 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
     constexpr int CPU = Unit<R>::CPU;
     constexpr int CG = 64 / NB;              // lanes per row (column) in wave 0
     constexpr int PER = (NB + CG - 1) / CG;  // columns (rows) per lane of a group
-    constexpr int RL = 192 / NB;             // threads per column in the far sums
+    constexpr int RL = SWEEP_BULK / NB;      // threads per column in the far sums
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int m = st.m, kd = st.n, n_x = m * m, ld = kd + 1;
     const int msk = Sz - 1;
@@ -520,9 +522,9 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
     const double2* g = reinterpret_cast<const double2*>(G) + (size_t)l * n_x;
     double2* u = reinterpret_cast<double2*>(U) + (size_t)l * n_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const bool producer = wave >= 4;
-    const int ptid = tid - 256;           // producer thread index
-    const int t1 = tid - 64;              // thread index within waves 1-3
+    const bool producer = wave >= 5;
+    const int ptid = tid - 64 - SWEEP_BULK;  // producer thread index
+    const int t1 = tid - 64;                 // thread index within waves 1-4
     const int npanel = (n_x + NB - 1) / NB;
     const cpx<R> cz = {R(0), R(0)};
 
@@ -534,7 +536,7 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
         const int units = (nb * ld + CPU - 1) / CPU;
         const UT* src = reinterpret_cast<const UT*>(Lb + (size_t)k * ld);
 #pragma unroll
-        for (int j = 0; j < SWEEP_QL; ++j) q[j] = src[min(ptid + 256 * j, units - 1)];
+        for (int j = 0; j < SWEEP_QL; ++j) q[j] = src[min(ptid + SWEEP_PROD * j, units - 1)];
     };
     auto pstore = [&](int p, int slot) {
         const int k = p * NB, nb = min(NB, n_x - k);
@@ -542,7 +544,7 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
         UT* dst = ring + slot * slot_units;
 #pragma unroll
         for (int j = 0; j < SWEEP_QL; ++j) {
-            const int e = ptid + 256 * j;
+            const int e = ptid + SWEEP_PROD * j;
             if (e < units) dst[e] = q[j];
         }
     };
@@ -560,7 +562,7 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
         pload(1);
     } else {
         const int rows0 = min(NB + kd, n_x);
-        for (int e = tid; e < NR * rows0; e += 256) {
+        for (int e = tid; e < NR * rows0; e += 64 + SWEEP_BULK) {
             const int rh = e / rows0, i = e - rh * rows0;
             const double2 v = g[(size_t)rh * rstride + i];
             Y[rh * Sz + (i & msk)] = {(R)v.x, (R)v.y};
@@ -621,7 +623,7 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
                     cpx<R> yq[NB];                            // y of panel p-1
 #pragma unroll
                     for (int c = 0; c < NB; ++c) yq[c] = Y[(kp + c) & msk];
-                    for (int i = k + NB + t1; i <= ihi; i += 192) {
+                    for (int i = k + NB + t1; i <= ihi; i += SWEEP_BULK) {
                         const int rr = i - kp;                // row offset in panel p-1
                         cpx<R> acc = cz;
 #pragma unroll
@@ -631,7 +633,7 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
                         yi = csub(yi, acc);
                     }
                 } else {
-                    for (int i = k + NB + t1; i <= ihi; i += 192) {
+                    for (int i = k + NB + t1; i <= ihi; i += SWEEP_BULK) {
                         const int rr = i - kp;
                         cpx<R> acc[NR];
 #pragma unroll
@@ -683,7 +685,7 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
             zc[rh] = {(R)z.x, (R)z.y};
         }
     } else {
-        for (int e = t1; e < RL * NR * NB; e += 192) P[e] = cz;
+        for (int e = t1; e < RL * NR * NB; e += SWEEP_BULK) P[e] = cz;
     }
     lds_barrier();
     for (int b = 0; b < npanel; ++b) {
@@ -712,7 +714,7 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
 #pragma unroll
             for (int rh = 0; rh < NR; ++rh) {
                 group_sum<CG>(acc[rh]);
-#pragma unroll 4
+#pragma unroll(16 / NR)
                 for (int t = 0; t < RL; ++t) {                // far sums
                     const cpx<R> f = Pr[(t * NR + rh) * NB + c];
                     acc[rh].x += f.x;
@@ -754,6 +756,7 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
 #pragma unroll
             for (int rh = 0; rh < NR; ++rh) part[rh] = cz;
             int j = far_period > 0 ? (rl + c) % far_period : 0;
+#pragma unroll 4
             for (int j0 = rl; j0 < far_period; j0 += RL) {
                 const int i = k + NB + j;
                 if (i <= ilast) {
@@ -1121,7 +1124,7 @@ size_t sweep_lds_bytes(int kd, int& Sz) {
     while (Sz < kd + 2 * NB) Sz <<= 1;
     constexpr int CPU = Unit<R>::CPU;
     const size_t slot = (size_t)(NB * (kd + 1) + CPU - 1) / CPU;   // 16-byte units
-    return 3 * slot * 16 + ((size_t)NR * Sz + 2 * (size_t)(192 / NB) * NR * NB) * sizeof(cpx<R>);
+    return 3 * slot * 16 + ((size_t)NR * Sz + 2 * (size_t)(SWEEP_BULK / NB) * NR * NB) * sizeof(cpx<R>);
 }
 constexpr size_t SWEEP_LDS_CAP = 160u * 1024u;
 
@@ -1130,7 +1133,7 @@ hipError_t launch_sweep_nr(const void* band, int count, const Stencil& st, const
                            long long rstride, hipStream_t s) {
     int Sz = 0;
     const size_t lds = sweep_lds_bytes<R, NB, NR>(st.n, Sz);
-    if ((size_t)NB * (st.n + 1) > (size_t)SWEEP_QL * 256 * Unit<R>::CPU || lds > SWEEP_LDS_CAP)
+    if ((size_t)NB * (st.n + 1) > (size_t)SWEEP_QL * SWEEP_PROD * Unit<R>::CPU || lds > SWEEP_LDS_CAP)
         return hipErrorInvalidValue;
     auto kern = conj ? k_sweep<R, NB, NR, true> : k_sweep<R, NB, NR, false>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1175,7 +1178,7 @@ hipError_t launch_sweep_nb(const void* band, int count, const Stencil& st, const
 template <class R>
 hipError_t launch_sweep(const void* band, int count, const Stencil& st, const double* G, double* U, int nrhs, int conj,
                         hipStream_t s) {
-    const size_t cap = (size_t)SWEEP_QL * 256 * Unit<R>::CPU;
+    const size_t cap = (size_t)SWEEP_QL * SWEEP_PROD * Unit<R>::CPU;
     const size_t ld = st.n + 1;
     const int kd = st.n;
     if (16 <= kd && 16 * ld <= cap) return launch_sweep_nb<R, 16>(band, count, st, G, U, nrhs, conj, s);
