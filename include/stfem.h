@@ -87,6 +87,11 @@ typedef struct stfem_options {
     int refine;         /* STFEM_REFINE_GMRES (0, default) or STFEM_REFINE_PLAIN   */
     int restart;        /* GMRES: applications of the inverse per cycle before a
                            restart; 0 = automatic (1 + max_iter, at most 23)       */
+    double factor_budget; /* bytes of device memory for factor storage; 0 = the
+                           free memory less the solve workspaces.  When the
+                           factors of all n_t blocks exceed it, fdm_factor keeps
+                           storage for one chunk of eigen-indices and every
+                           solve factors the chunks again, one after the other */
 } stfem_options;
 
 typedef struct stfem_report {
@@ -105,7 +110,10 @@ typedef struct stfem_report {
     double ms_residual;     /* all residual kernels of this call                  */
     double history[16];     /* relative residual after each of the first 16
                                applications of the inverse (GMRES: its own
-                               estimate; unused entries are -1)                    */
+                               estimate; chunked factors: after each round;
+                               unused entries are -1)                              */
+    int chunks;             /* chunks of eigen-indices the factors were computed in
+                               (1: all blocks factored once in fdm_factor)         */
 } stfem_report;
 
 typedef struct stfem_handle stfem_handle;   /* FDM solver: X, W, lambda, factors */

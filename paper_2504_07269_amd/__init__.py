@@ -84,7 +84,7 @@ class FDM:
     REFINE = {"gmres": 0, "plain": 1}
 
     def __init__(self, M_t, B_t, M_st, A_st, n, precision=64, tol=1e-10, max_iter=30, stream=None, refine="gmres",
-                 restart=0):
+                 restart=0, factor_budget=0.0):
         M_t = np.ascontiguousarray(M_t, dtype=np.float64)
         B_t = np.ascontiguousarray(B_t, dtype=np.float64)
         M_st = np.ascontiguousarray(M_st, dtype=np.float64)
@@ -94,7 +94,8 @@ class FDM:
             raise ValueError("temporal matrices must be square and equal in size")
         if refine not in self.REFINE:
             raise ValueError("refine must be one of %s" % sorted(self.REFINE))
-        opt = Options(int(precision), int(max_iter), float(tol), self.REFINE[refine], int(restart))
+        opt = Options(int(precision), int(max_iter), float(tol), self.REFINE[refine], int(restart),
+                      float(factor_budget))
         h = ctypes.c_void_p()
         check(lib().fdm_factor(dptr(M_t), dptr(B_t), nt, dptr(M_st), dptr(A_st), int(n), ctypes.byref(opt),
                                _stream(stream), ctypes.byref(h)))
@@ -162,8 +163,8 @@ class FDM:
 
 
 def fdm_factor(M_t, B_t, M_st, A_st, n, precision=64, tol=1e-10, max_iter=30, stream=None, refine="gmres",
-               restart=0):
-    return FDM(M_t, B_t, M_st, A_st, n, precision, tol, max_iter, stream, refine, restart)
+               restart=0, factor_budget=0.0):
+    return FDM(M_t, B_t, M_st, A_st, n, precision, tol, max_iter, stream, refine, restart, factor_budget)
 
 
 def fdm_solve(h, F, out=None, stream=None):

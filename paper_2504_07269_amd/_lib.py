@@ -26,7 +26,7 @@ class StfemError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
-                ("refine", ctypes.c_int), ("restart", ctypes.c_int)]
+                ("refine", ctypes.c_int), ("restart", ctypes.c_int), ("factor_budget", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
@@ -34,7 +34,7 @@ class Report(ctypes.Structure):
                 ("ms_eig", ctypes.c_double), ("ms_factor", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("ms_band_fill", ctypes.c_double), ("ms_ldlt", ctypes.c_double), ("ms_sweeps", ctypes.c_double),
                 ("ms_transforms", ctypes.c_double), ("ms_residual", ctypes.c_double),
-                ("history", ctypes.c_double * 16)]
+                ("history", ctypes.c_double * 16), ("chunks", ctypes.c_int)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "history"}

@@ -76,6 +76,13 @@ hipError_t vec_norm2(const double* x, long long N, int nrhs, double* partial, do
 // y[r] = sc[r] x[r], sc real [nrhs] on the device; y may equal x
 hipError_t vec_scale(double* y, const double* x, long long N, int nrhs, const double* sc, hipStream_t s);
 
+// Shifted spatial blocks of a chunk, FP64: for systems s < nsys (each n_x
+// complex128), l = l0 + s % cnt, S_l = lambda_l M + A (conj: conj(lambda_l));
+// Y_s = S_l X_s, or Y_s = B_s - S_l X_s when B != null.  lambda: device
+// complex128 of all eigen-indices.
+hipError_t shifted_apply(const Stencil& st, const double* lambda, int l0, int cnt, int conj, const double* X,
+                         double* Y, const double* B, int nsys, hipStream_t s);
+
 // p[0..count) = value (a kernel, so that it may be recorded in a graph).
 hipError_t fill_int(int* p, int count, int value, hipStream_t s);
 

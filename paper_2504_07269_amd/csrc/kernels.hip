@@ -965,11 +965,34 @@ __global__ __launch_bounds__(256) void k_spatial(const double2* __restrict__ X, 
                                ar * Mv.y + ai * Mv.x + br * Av.y + bi * Av.x);
 }
 
+// Shifted spatial blocks of one chunk of eigen-indices, in FP64: system s
+// (blockIdx.y) uses S_l = lambda_l M + A with l = l0 + s % cnt (conj:
+// conj(lambda_l) M + A); Y_s = S_l X_s, or Y_s = B_s - S_l X_s if B != null.
+__global__ __launch_bounds__(256) void k_shifted(const double2* __restrict__ X, double2* __restrict__ Y,
+                                                 const double2* __restrict__ B, const double* __restrict__ lam,
+                                                 int l0, int cnt, int conj, Stencil st) {
+    const int n_x = st.m * st.m;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= n_x) return;
+    const int sy = blockIdx.y;
+    const size_t base = (size_t)sy * n_x;
+    const int l = l0 + sy % cnt;
+    const double lr = lam[2 * l], li = conj ? -lam[2 * l + 1] : lam[2 * l + 1];
+    double2 Mv, Av;
+    stencil_apply(X + base, x, st.m, st, Mv, Av);
+    double2 v = make_double2(lr * Mv.x - li * Mv.y + Av.x, lr * Mv.y + li * Mv.x + Av.y);
+    if (B) {
+        const double2 b = B[base + x];
+        v = make_double2(b.x - v.x, b.y - v.y);
+    }
+    Y[base + x] = v;
+}
+
 // ------------------------------------------------------------- Krylov vectors
-// Space-time vectors of the refinement: complex128, nrhs slices of N
-// elements (slice r at offset r*N).  A basis holds nv such vectors, vstride
-// complex elements apart.  Every reduction runs over VEC_BLOCKS workgroups per
-// rhs, then k_partial_reduce sums their partial results.
+// Vectors of the Krylov solvers: complex128, nrhs slices of N elements (slice
+// r at offset r*N).  A basis holds nv such vectors, vstride complex elements
+// apart.  Every reduction runs over gridDim.x (<= VEC_BLOCKS) workgroups per
+// slice, then k_partial_reduce sums their partial results.
 
 // Sum of a 64-lane wave, then of the 4 waves of a 256-thread workgroup
 // (result valid in thread 0).  `red` holds 4 doubles.
@@ -982,7 +1005,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return red[0] + red[1] + red[2] + red[3];
 }
 
-// partial[(r*VEC_BLOCKS + bx)*2nv + 2i + {0,1}] = workgroup share of
+// partial[(r*gridDim.x + bx)*2nv + 2i + {0,1}] = workgroup share of
 // sum_e conj(V_i[r][e]) w[r][e]
 __global__ __launch_bounds__(256) void k_mdot(const double2* __restrict__ V, long long vstride, int nv,
                                               const double2* __restrict__ w, long long N,
@@ -993,7 +1016,7 @@ __global__ __launch_bounds__(256) void k_mdot(const double2* __restrict__ V, lon
     double2 acc[KRYLOV_MAX];
 #pragma unroll
     for (int i = 0; i < KRYLOV_MAX; ++i) acc[i] = make_double2(0.0, 0.0);
-    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long long)VEC_BLOCKS * 256) {
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long long)gridDim.x * 256) {
         const double2 x = wr[e];
 #pragma unroll
         for (int i = 0; i < KRYLOV_MAX; ++i) {
@@ -1005,7 +1028,7 @@ __global__ __launch_bounds__(256) void k_mdot(const double2* __restrict__ V, lon
         }
     }
     __shared__ double red[4];
-    double* out = partial + ((size_t)r * VEC_BLOCKS + blockIdx.x) * 2 * nv;
+    double* out = partial + ((size_t)r * gridDim.x + blockIdx.x) * 2 * nv;
 #pragma unroll
     for (int i = 0; i < KRYLOV_MAX; ++i) {
         if (i < nv) {
@@ -1034,7 +1057,7 @@ __global__ __launch_bounds__(256) void k_mcomb(double2* __restrict__ w, long lon
     }
     __syncthreads();
     double nrm = 0.0;
-    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long long)VEC_BLOCKS * 256) {
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long long)gridDim.x * 256) {
         double2 x = accumulate ? wr[e] : make_double2(0.0, 0.0);
 #pragma unroll
         for (int i = 0; i < KRYLOV_MAX; ++i) {
@@ -1050,7 +1073,7 @@ __global__ __launch_bounds__(256) void k_mcomb(double2* __restrict__ w, long lon
     if (partial) {
         __shared__ double red[4];
         const double t = block_sum(nrm, red);
-        if (threadIdx.x == 0) partial[(size_t)r * VEC_BLOCKS + blockIdx.x] = t;
+        if (threadIdx.x == 0) partial[(size_t)r * gridDim.x + blockIdx.x] = t;
     }
 }
 
@@ -1060,33 +1083,33 @@ __global__ __launch_bounds__(256) void k_vnorm2(const double2* __restrict__ x, l
     const int r = blockIdx.y;
     const double2* xr = x + (size_t)r * N;
     double nrm = 0.0;
-    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long long)VEC_BLOCKS * 256) {
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long long)gridDim.x * 256) {
         const double2 v = xr[e];
         nrm += v.x * v.x + v.y * v.y;
     }
     __shared__ double red[4];
     const double t = block_sum(nrm, red);
-    if (threadIdx.x == 0) partial[(size_t)r * VEC_BLOCKS + blockIdx.x] = t;
+    if (threadIdx.x == 0) partial[(size_t)r * gridDim.x + blockIdx.x] = t;
 }
 
 // y[r] = sc[r] x[r] (sc real, on the device); y may equal x
 __global__ __launch_bounds__(256) void k_vscale(double2* y, const double2* x, long long N, const double* sc) {
     const int r = blockIdx.y;
     const double a = sc[r];
-    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long long)VEC_BLOCKS * 256) {
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long long)gridDim.x * 256) {
         const double2 v = x[(size_t)r * N + e];
         y[(size_t)r * N + e] = make_double2(a * v.x, a * v.y);
     }
 }
 
-// out[r*width + c] = sum over the VEC_BLOCKS shares partial[(r*VEC_BLOCKS + b)*width + c]
-__global__ __launch_bounds__(256) void k_partial_reduce(const double* __restrict__ partial, int width,
+// out[r*width + c] = sum over the nblk shares partial[(r*nblk + b)*width + c]
+__global__ __launch_bounds__(256) void k_partial_reduce(const double* __restrict__ partial, int nblk, int width,
                                                         double* __restrict__ out) {
     const int r = blockIdx.x;
     __shared__ double red[4];
     for (int c = 0; c < width; ++c) {
         double v = 0.0;
-        for (int b = threadIdx.x; b < VEC_BLOCKS; b += 256) v += partial[((size_t)r * VEC_BLOCKS + b) * width + c];
+        for (int b = threadIdx.x; b < nblk; b += 256) v += partial[((size_t)r * nblk + b) * width + c];
         const double t = block_sum(v, red);
         if (threadIdx.x == 0) out[(size_t)r * width + c] = t;
     }
@@ -1267,38 +1290,53 @@ hipError_t spatial_apply(const Stencil& st, double ar, double ai, double br, dou
 
 size_t krylov_partial_size(int nrhs) { return (size_t)nrhs * VEC_BLOCKS * 2 * KRYLOV_MAX; }
 
+// workgroups per slice: about 8 elements per thread, at most VEC_BLOCKS
+static int vec_grid(long long N) { return (int)std::min<long long>(VEC_BLOCKS, std::max<long long>(1, (N + 2047) / 2048)); }
+
 hipError_t vec_mdot(const double* V, long long vstride, int nv, const double* w, long long N, int nrhs,
                     double* partial, double* out, hipStream_t s) {
     if (nv < 1 || nv > KRYLOV_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_mdot, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, s, (const double2*)V, vstride, nv,
-                       (const double2*)w, N, partial);
+    const int vb = vec_grid(N);
+    hipLaunchKernelGGL(k_mdot, dim3(vb, nrhs), dim3(256), 0, s, (const double2*)V, vstride, nv, (const double2*)w, N,
+                       partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_partial_reduce, dim3(nrhs), dim3(256), 0, s, (const double*)partial, 2 * nv, out);
+    hipLaunchKernelGGL(k_partial_reduce, dim3(nrhs), dim3(256), 0, s, (const double*)partial, vb, 2 * nv, out);
     return hipGetLastError();
 }
 
 hipError_t vec_mcomb(double* w, long long N, int nrhs, const double* V, long long vstride, int nv, const double* coef,
                      double sign, int accumulate, double* partial, double* norms, hipStream_t s) {
     if (nv < 0 || nv > KRYLOV_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_mcomb, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, s, (double2*)w, N, (const double2*)V, vstride,
-                       nv, (const double2*)coef, sign, accumulate, norms ? partial : (double*)nullptr);
+    const int vb = vec_grid(N);
+    hipLaunchKernelGGL(k_mcomb, dim3(vb, nrhs), dim3(256), 0, s, (double2*)w, N, (const double2*)V, vstride, nv,
+                       (const double2*)coef, sign, accumulate, norms ? partial : (double*)nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !norms) return e;
-    hipLaunchKernelGGL(k_partial_reduce, dim3(nrhs), dim3(256), 0, s, (const double*)partial, 1, norms);
+    hipLaunchKernelGGL(k_partial_reduce, dim3(nrhs), dim3(256), 0, s, (const double*)partial, vb, 1, norms);
     return hipGetLastError();
 }
 
 hipError_t vec_norm2(const double* x, long long N, int nrhs, double* partial, double* norms, hipStream_t s) {
-    hipLaunchKernelGGL(k_vnorm2, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, s, (const double2*)x, N, partial);
+    const int vb = vec_grid(N);
+    hipLaunchKernelGGL(k_vnorm2, dim3(vb, nrhs), dim3(256), 0, s, (const double2*)x, N, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_partial_reduce, dim3(nrhs), dim3(256), 0, s, (const double*)partial, 1, norms);
+    hipLaunchKernelGGL(k_partial_reduce, dim3(nrhs), dim3(256), 0, s, (const double*)partial, vb, 1, norms);
     return hipGetLastError();
 }
 
 hipError_t vec_scale(double* y, const double* x, long long N, int nrhs, const double* sc, hipStream_t s) {
-    hipLaunchKernelGGL(k_vscale, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, s, (double2*)y, (const double2*)x, N, sc);
+    hipLaunchKernelGGL(k_vscale, dim3(vec_grid(N), nrhs), dim3(256), 0, s, (double2*)y, (const double2*)x, N, sc);
+    return hipGetLastError();
+}
+
+hipError_t shifted_apply(const Stencil& st, const double* lambda, int l0, int cnt, int conj, const double* X,
+                         double* Y, const double* B, int nsys, hipStream_t s) {
+    const int n_x = st.m * st.m;
+    if (nsys < 1 || nsys > 65535 || cnt < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_shifted, dim3((n_x + 255) / 256, nsys), dim3(256), 0, s, (const double2*)X, (double2*)Y,
+                       (const double2*)B, lambda, l0, cnt, conj, st);
     return hipGetLastError();
 }
 

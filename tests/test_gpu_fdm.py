@@ -150,3 +150,42 @@ def test_gmres_restarts_and_multiple_rhs_converge():
     assert np.all(Psi[1] == 0)
     for r in (0, 2):
         assert solvers.relres(Mt, Bt, Mx, Ax, Psi[r], F[r]) <= 2e-13
+
+
+def _block_bytes(n, precision):
+    return (((n - 1) ** 2 * (n + 1) + 63) // 64 * 64) * (8 if precision == 32 else 16)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_chunked_factors_match_dense(precision):
+    """A factor budget of 6 blocks splits the 16 eigen-indices into chunks of
+    6, 6, 4 that are factored again in every solve; forward and adjoint must
+    still equal the dense global solves."""
+    nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(16, 16)
+    F = oracle_rhs_c0()
+    h = st.fdm_factor(Mt, Bt, Ms, As, 16, precision=precision, tol=1e-12, max_iter=40,
+                      factor_budget=6 * _block_bytes(16, precision) + 100)
+    Psi = to_host(h.solve(to_dev(F)))
+    assert relerr(Psi, solvers.solve_dense(Mt, Bt, Mx, Ax, F)) < 1e-10
+    assert h.last_report["rel_residual"] <= 1e-12
+    G = synth.random_rhs(3, 16, 225)
+    Lam = to_host(h.solve_adjoint(to_dev(G)))
+    assert relerr(Lam, solvers.solve_dense_adjoint(Mt, Bt, Mx, Ax, G)) < 1e-10
+    with pytest.raises(st.StfemError) as e:
+        st.fdm_factor(Mt, Bt, Ms, As, 16, precision=precision, factor_budget=_block_bytes(16, precision) // 2)
+    assert e.value.status == -2
+
+
+def test_chunked_c1_five_rhs():
+    """n=128, N_t=128 in three chunks, FP32 factors: every rhs reaches 1e-10."""
+    wl = synth.WORKLOADS["c1"]
+    nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(wl.n, wl.N_t, wl.T)
+    F = np.concatenate([synth.manufactured_rhs(wl)[None],
+                        np.stack([synth.random_rhs(s, wl.n_t, wl.n_x) for s in range(4)])])
+    h = st.fdm_factor(Mt, Bt, Ms, As, wl.n, precision=32, tol=1e-10, max_iter=40,
+                      factor_budget=43 * _block_bytes(wl.n, 32) + 100)
+    Psi = to_host(h.solve(to_dev(F)))
+    R = F - solvers.apply_global_structured(Mt, Bt, Mx, Ax, Psi)
+    for r in range(5):
+        assert np.linalg.norm(R[r]) / np.linalg.norm(F[r]) <= 1e-10
+    assert relerr(Psi[0], solvers.fdm_paper(Mt, Bt, Mx, Ax, F[0])) < 1e-8
