@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
     const int m = st.m, kd = st.n, n_x = m * m, ld = kd + 1;
     cpx<R>* Pb = reinterpret_cast<cpx<R>*>(smem_raw);                 // NB*ld, rounded to units
     cpx<R>* Dinv = Pb + (NB * ld + CPU - 1) / CPU * CPU;             // NB
-    R* Bsw = reinterpret_cast<R*>(Dinv + NB);                         // ceil(kd/TS) * 64 * KS
+    cpx<R>* Nsw = Dinv + NB;                                          // ceil(kd/TS) * TS * NB
     const int l = blockIdx.x;
     cpx<R>* A = band + (size_t)l * band_stride(st);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -364,51 +364,57 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
             const UT* src = reinterpret_cast<const UT*>(Pb);
             for (int e = tid; e < units; e += 256) dst[e] = src[e];
         }
-        // ---- 4. B' operands of every tile column, once for all waves:
-        //      Bsw[(J*64 + lane)*KS + s] is what `lane` feeds the matrix cores
-        //      at k step s for tile column J
+        // ---- 4. A' operands, once for all waves: N = -(L D) of every row of
+        //      the trailing window, Nsw[((J*RB + rb)*NB + c)*ROWS + i] for
+        //      window row TS*J + ROWS*rb + i and panel column c
         const int ntr = mrows - nb;               // trailing rows/cols
         const int TT = (ntr + TS - 1) / TS;       // tile rows
-        for (int e = tid; e < TT * 64 * KS; e += 256) {
-            const int s = e % KS, ln = (e / KS) & 63, J = e / (KS * 64);
-            const int c = s * MM::KC + MM::b_k(ln), cc = TS * J + MM::b_col(ln);
-            const cpx<R> qv = (cc < ntr && c < nb) ? PV(c, nb + cc) : zero;
-            Bsw[e] = MM::b_b(ln) ? qv.y : qv.x;
+        for (int e = tid; e < TT * TS * NB; e += 256) {
+            const int i = e % MM::ROWS, c = (e / MM::ROWS) % NB, jb = e / (MM::ROWS * NB);
+            const int rr = MM::ROWS * jb + i;
+            cpx<R> pv = zero;
+            if (rr < ntr && c < nb) pv = cmul(Pb[c * ld], PV(c, nb + rr));
+            Nsw[e] = cpx<R>{-pv.x, -pv.y};
         }
         lds_barrier();
-        // ---- 5. trailing update on the matrix cores
+        // ---- 5. trailing update on the matrix cores, tile (I, J), J <= I, of
+        //      the lower triangle computed transposed, C^T += N_J L_I^T: a lane
+        //      then owns one row of the tile, and its loads and stores of the
+        //      tile run down the band columns (contiguous).  The 2x2 real block
+        //      of a complex N entry is [[x, -y], [y, x]]; a lane's A' element is
+        //      component a_im ^ a_b of N, negated for (a_im, a_b) = (0, 1).
+        const R* Nf = reinterpret_cast<const R*>(Nsw);
+        const int a_off = 2 * (MM::a_k(lane) * MM::ROWS + MM::a_row(lane)) + (MM::a_im(lane) ^ MM::a_b(lane));
+        const R a_sgn = (MM::a_b(lane) && !MM::a_im(lane)) ? R(-1) : R(1);
         const int npairs = (TT + 2 * NW - 1) / (2 * NW);
         for (int q = 0; q < 2 * npairs; ++q) {
             const int p = q >> 1;
             const int I = (q & 1) ? 2 * NW * p + 2 * NW - 1 - wave : 2 * NW * p + wave;
             if (I >= TT) continue;
-            // A' operands of tile row I: -(L D) in 2x2 real-block form
-            R av[RB][KS];
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const int rr = TS * I + MM::ROWS * rb + MM::a_row(lane);
+            // B' operands of tile row I: L in real/imaginary parts
+            R bv[KS];
+            {
+                const int rr = TS * I + MM::b_col(lane);
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
-                    const int c = s * MM::KC + MM::a_k(lane);
-                    cpx<R> pv = zero;
-                    if (rr < ntr && c < nb) pv = cmul(Pb[c * ld], PV(c, nb + rr));
-                    const int im = MM::a_im(lane), b = MM::a_b(lane);
-                    av[rb][s] = (im == b) ? -pv.x : (im ? -pv.y : pv.y);
+                    const int c = s * MM::KC + MM::b_k(lane);
+                    const cpx<R> lv = (rr < ntr && c < nb) ? PV(c, nb + rr) : zero;
+                    bv[s] = MM::b_b(lane) ? lv.y : lv.x;
                 }
             }
             const bool rows_full = TS * (I + 1) <= ntr;
-            // row of accumulator entry e of row block rb, relative to the tile
-            auto trow = [&](int rb, int e) { return MM::ROWS * rb + MM::e_row(lane, e); };
-            // C tile (I, J) into registers; zero outside the lower triangle
+            const int brow = TS * I + MM::c_col(lane);   // window row held by this lane
+            // window column of accumulator entry e of row block rb, relative to tile column J
+            auto tcol = [&](int rb, int e) { return MM::ROWS * rb + MM::e_row(lane, e); };
+            // band address of window entry (brow, col): column-major lower band
+            auto addr = [&](int col) { return A + (size_t)(k + nb + col) * ld + (brow - col); };
             auto load_c = [&](int J, typename MM::acc_t (&acc)[RB]) {
-                const int cc = TS * J + MM::c_col(lane);
-                cpx<R>* col = A + (size_t)(k + nb + cc) * ld - cc + TS * I;
                 if (J < I && rows_full) {
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                         for (int e = 0; e < MM::NENT; ++e) {
-                            const cpx<R> cv = col[trow(rb, e)];
+                            const cpx<R> cv = *addr(TS * J + tcol(rb, e));
                             acc[rb][MM::e_re(e)] = cv.x;
                             acc[rb][MM::e_im(e)] = cv.y;
                         }
@@ -417,31 +423,29 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
                     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                         for (int e = 0; e < MM::NENT; ++e) {
-                            const int rr = TS * I + trow(rb, e);
+                            const int cc = TS * J + tcol(rb, e);
                             cpx<R> cv = zero;
-                            if (J <= I && rr < ntr && cc < ntr && rr >= cc) cv = col[trow(rb, e)];
+                            if (J <= I && brow < ntr && cc < ntr && brow >= cc) cv = *addr(cc);
                             acc[rb][MM::e_re(e)] = cv.x;
                             acc[rb][MM::e_im(e)] = cv.y;
                         }
                 }
             };
             auto store_c = [&](int J, const typename MM::acc_t (&acc)[RB]) {
-                const int cc = TS * J + MM::c_col(lane);
-                cpx<R>* col = A + (size_t)(k + nb + cc) * ld - cc + TS * I;
                 if (J < I && rows_full) {
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                         for (int e = 0; e < MM::NENT; ++e)
-                            col[trow(rb, e)] = cpx<R>{acc[rb][MM::e_re(e)], acc[rb][MM::e_im(e)]};
+                            *addr(TS * J + tcol(rb, e)) = cpx<R>{acc[rb][MM::e_re(e)], acc[rb][MM::e_im(e)]};
                 } else {
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                         for (int e = 0; e < MM::NENT; ++e) {
-                            const int rr = TS * I + trow(rb, e);
-                            if (rr < ntr && cc < ntr && rr >= cc)
-                                col[trow(rb, e)] = cpx<R>{acc[rb][MM::e_re(e)], acc[rb][MM::e_im(e)]};
+                            const int cc = TS * J + tcol(rb, e);
+                            if (brow < ntr && cc < ntr && brow >= cc)
+                                *addr(cc) = cpx<R>{acc[rb][MM::e_re(e)], acc[rb][MM::e_im(e)]};
                         }
                 }
             };
@@ -449,20 +453,13 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
             load_c(0, acc);
             for (int J = 0; J <= I; ++J) {
                 load_c(J + 1, accn);                 // next tile, in flight during the MFMAs
-                R bv[KS];
-                const typename Unit<R>::T* bsrc =
-                    reinterpret_cast<const typename Unit<R>::T*>(Bsw + (size_t)(J * 64 + lane) * KS);
-                constexpr int RPU = 16 / sizeof(R);  // reals per 16-byte unit
-#pragma unroll
-                for (int s = 0; s < KS / RPU; ++s) {
-                    const typename Unit<R>::T v = bsrc[s];
-#pragma unroll
-                    for (int t = 0; t < RPU; ++t) bv[RPU * s + t] = v[t];
-                }
 #pragma unroll
                 for (int s = 0; s < KS; ++s)
 #pragma unroll
-                    for (int rb = 0; rb < RB; ++rb) acc[rb] = MM::mma(av[rb][s], bv[s], acc[rb]);
+                    for (int rb = 0; rb < RB; ++rb) {
+                        const R av = a_sgn * Nf[((J * RB + rb) * NB + s * MM::KC) * MM::ROWS * 2 + a_off];
+                        acc[rb] = MM::mma(av, bv[s], acc[rb]);
+                    }
                 store_c(J, acc);
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) acc[rb] = accn[rb];
@@ -1127,7 +1124,7 @@ size_t ldlt_lds_bytes(int kd) {
     constexpr int CPU = Unit<R>::CPU;
     const size_t panel = (size_t)(NB * (kd + 1) + CPU - 1) / CPU * CPU + NB;
     const size_t tiles = (size_t)(kd + Mma<R>::COLS - 1) / Mma<R>::COLS;
-    return panel * sizeof(cpx<R>) + tiles * 64 * (NB / Mma<R>::KC) * sizeof(R);
+    return (panel + tiles * Mma<R>::COLS * NB) * sizeof(cpx<R>);
 }
 
 template <class R, int NB>
