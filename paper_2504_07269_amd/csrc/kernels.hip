@@ -253,6 +253,22 @@ __device__ __forceinline__ void wave_sync() {
 //     tile row's A' operands in registers and sweeps that row's tiles, loading
 //     the next tile while the current one is in the matrix pipe; tile rows are
 //     paired (I, T-1-I) across waves for balance.
+// One row of the panel below its diagonal block: x[C] = (x[C] - sum_{c2<C}
+// x[c2] W[C][c2]) D^{-1}_C for C = 0..NB-1, unrolled at compile time so that
+// the row stays in registers.
+template <int C, int NB, class R>
+__device__ __forceinline__ void row_solve(cpx<R> (&x)[NB], const cpx<R>* W, const cpx<R>* Dinv) {
+    if constexpr (C < NB) {
+#pragma unroll
+        for (int c2 = 0; c2 < C; ++c2) x[C] = csub(x[C], cmul(x[c2], W[C * NB + c2]));
+        x[C] = cmul(x[C], Dinv[C]);
+        // finish this column before the next column's table reads, or all
+        // NB^2/2 of them would be in registers at once
+        __asm__ volatile("" : "+v"(x[C].x), "+v"(x[C].y) : : "memory");
+        row_solve<C + 1, NB>(x, W, Dinv);
+    }
+}
+
 template <class R, int NB>
 __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Stencil st, int* __restrict__ info) {
     typedef Mma<R> MM;
@@ -266,7 +282,8 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
     const int m = st.m, kd = st.n, n_x = m * m, ld = kd + 1;
     cpx<R>* Pb = reinterpret_cast<cpx<R>*>(smem_raw);                 // NB*ld, rounded to units
     cpx<R>* Dinv = Pb + (NB * ld + CPU - 1) / CPU * CPU;             // NB
-    cpx<R>* Nsw = Dinv + NB;                                          // ceil(kd/TS) * TS * NB
+    cpx<R>* W = Dinv + NB;                                            // NB * NB
+    cpx<R>* Nsw = W + NB * NB;                                        // ceil(kd/TS) * TS * NB
     const int l = blockIdx.x;
     cpx<R>* A = band + (size_t)l * band_stride(st);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -332,30 +349,22 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
             }
         }
         lds_barrier();
-        // ---- 2. rows below the diagonal block, 8 columns at a time; the
-        //      finished columns hold y = L D until the final scaling by D^{-1}
+        // ---- 2. rows below the diagonal block, one row per thread in
+        //      registers: L[r][c] = (A[r][c] - sum_{c2<c} L[r][c2] W[c][c2]) / D_c
+        //      with W[c][c2] = D_c2 L[c][c2] from the diagonal block
+        for (int e = tid; e < NB * NB; e += 256) {
+            const int c = e / NB, c2 = e - c * NB;
+            W[e] = (c2 < c && c < nb) ? cmul(Pb[c2 * ld], Pb[c2 * ld + (c - c2)]) : zero;
+        }
+        lds_barrier();
         for (int r = nb + tid; r < mrows; r += 256) {
-            for (int c0 = 0; c0 < nb; c0 += 8) {
-                cpx<R> y[8];
+            cpx<R> x[NB];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) y[u] = (c0 + u < nb) ? PV(c0 + u, r) : zero;
-#pragma unroll 4
-                for (int c2 = 0; c2 < c0; ++c2) {            // finished columns
-                    const cpx<R> yc = PV(c2, r);
+            for (int c = 0; c < NB; ++c) x[c] = (c < nb) ? PV(c, r) : zero;
+            row_solve<0, NB>(x, W, Dinv);
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) y[u] = csub(y[u], cmul(yc, Pb[c2 * ld + (c0 + u - c2)]));
-                }
-#pragma unroll
-                for (int u = 1; u < 8; ++u) {                // within the block
-#pragma unroll
-                    for (int v = 0; v < u; ++v) y[u] = csub(y[u], cmul(y[v], Pb[(c0 + v) * ld + (u - v)]));
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (c0 + u < nb && r - (c0 + u) <= kd) Pb[(c0 + u) * ld + (r - c0 - u)] = y[u];
-            }
-            for (int c = 0; c < nb; ++c)
-                if (r - c <= kd) Pb[c * ld + (r - c)] = cmul(Pb[c * ld + (r - c)], Dinv[c]);
+            for (int c = 0; c < NB; ++c)
+                if (c < nb && r - c <= kd) Pb[c * ld + (r - c)] = x[c];
         }
         lds_barrier();
         // ---- 3. panel chunk back to global memory
@@ -1124,7 +1133,7 @@ size_t ldlt_lds_bytes(int kd) {
     constexpr int CPU = Unit<R>::CPU;
     const size_t panel = (size_t)(NB * (kd + 1) + CPU - 1) / CPU * CPU + NB;
     const size_t tiles = (size_t)(kd + Mma<R>::COLS - 1) / Mma<R>::COLS;
-    return (panel + tiles * Mma<R>::COLS * NB) * sizeof(cpx<R>);
+    return (panel + (size_t)NB * NB + tiles * Mma<R>::COLS * NB) * sizeof(cpx<R>);
 }
 
 template <class R, int NB>
