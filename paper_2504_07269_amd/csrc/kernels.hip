@@ -42,6 +42,15 @@ template <class R>
 __device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) {
     return {a.x - b.x, a.y - b.y};
 }
+// y - a*b in four fused multiply-adds
+template <class R>
+__device__ __forceinline__ cpx<R> cfms(cpx<R> y, cpx<R> a, cpx<R> b) {
+    y.x = fma(-a.x, b.x, y.x);
+    y.x = fma(a.y, b.y, y.x);
+    y.y = fma(-a.x, b.y, y.y);
+    y.y = fma(-a.y, b.x, y.y);
+    return y;
+}
 template <class R>
 __device__ __forceinline__ cpx<R> cinv_or_zero(cpx<R> d, bool& ok) {
     const R dn = d.x * d.x + d.y * d.y;
@@ -260,7 +269,7 @@ template <int C, int NB, class R>
 __device__ __forceinline__ void row_solve(cpx<R> (&x)[NB], const cpx<R>* W, const cpx<R>* Dinv) {
     if constexpr (C < NB) {
 #pragma unroll
-        for (int c2 = 0; c2 < C; ++c2) x[C] = csub(x[C], cmul(x[c2], W[C * NB + c2]));
+        for (int c2 = 0; c2 < C; ++c2) x[C] = cfms(x[C], x[c2], W[C * NB + c2]);
         x[C] = cmul(x[C], Dinv[C]);
         // finish this column before the next column's table reads, or all
         // NB^2/2 of them would be in registers at once
@@ -283,7 +292,8 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
     cpx<R>* Pb = reinterpret_cast<cpx<R>*>(smem_raw);                 // NB*ld, rounded to units
     cpx<R>* Dinv = Pb + (NB * ld + CPU - 1) / CPU * CPU;             // NB
     cpx<R>* W = Dinv + NB;                                            // NB * NB
-    cpx<R>* Nsw = W + NB * NB;                                        // ceil(kd/TS) * TS * NB
+    cpx<R>* Xb = W + NB * NB;                                         // 2 * NB
+    cpx<R>* Nsw = Xb + 2 * NB;                                        // ceil(kd/TS) * TS * NB
     const int l = blockIdx.x;
     cpx<R>* A = band + (size_t)l * band_stride(st);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -318,7 +328,9 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
             }
         }
         lds_barrier();
-        // ---- 1. diagonal block (wave 0, lane r = row r)
+        // ---- 1. diagonal block (wave 0, lane r = row r): column by column,
+        //      the pivot by a lane broadcast, L[.][c] published through LDS
+        //      (Xb, double-buffered) and read back as broadcasts
         if (wave == 0) {
             const int r = lane;
             cpx<R> y[NB];
@@ -332,12 +344,12 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
                     const cpx<R> inv = cinv_or_zero(d, ok);
                     if (!ok && bad == 0) bad = k + c + 1;
                     const cpx<R> lr = cmul(y[c], inv);          // L[r][c] for r > c
-                    const cpx<R> ld_r = cmul(lr, d);            // L[r][c] D_c
+                    cpx<R>* xb = Xb + (c & 1) * NB;
+                    if (r < NB) xb[r] = lr;
+                    wave_sync();
 #pragma unroll
-                    for (int c2 = c + 1; c2 < NB; ++c2) {
-                        const cpx<R> lc2 = rdlane(lr, c2);      // L[c2][c]
-                        y[c2] = csub(y[c2], cmul(ld_r, lc2));
-                    }
+                    for (int c2 = c + 1; c2 < NB; ++c2)          // Y[r][c2] -= Y[r][c] L[c2][c]
+                        y[c2] = cfms(y[c2], y[c], xb[c2]);
                     if (r > c) y[c] = lr;
                     if (r == c) Dinv[c] = inv;
                 }
@@ -1133,7 +1145,7 @@ size_t ldlt_lds_bytes(int kd) {
     constexpr int CPU = Unit<R>::CPU;
     const size_t panel = (size_t)(NB * (kd + 1) + CPU - 1) / CPU * CPU + NB;
     const size_t tiles = (size_t)(kd + Mma<R>::COLS - 1) / Mma<R>::COLS;
-    return (panel + (size_t)NB * NB + tiles * Mma<R>::COLS * NB) * sizeof(cpx<R>);
+    return (panel + (size_t)NB * NB + 2 * NB + tiles * Mma<R>::COLS * NB) * sizeof(cpx<R>);
 }
 
 template <class R, int NB>
