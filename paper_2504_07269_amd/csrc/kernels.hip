@@ -248,20 +248,28 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // One workgroup (4 waves) factors one band as L D L^T, right-looking, NB
-// columns per step.  The NB columns of a step are one contiguous chunk of
-// band storage; they are copied to LDS as they are (Pb[c*ld + d] = entry
-// (k+c+d, k+c)) with 16-byte transfers, and per step:
-//  1. wave 0 factors the NB x NB diagonal block in registers (lane r holds
-//     row r, column multipliers are broadcast between lanes);
-//  2. every thread solves one row below the block, left-looking in
-//     registers: L[r][c] D_c = A[r][c] - sum_{c'<c} L[r][c'] D_c' L[c][c'];
-//  3. the chunk goes back to global memory (final L and D);
-//  4. the trailing kd x kd lower triangle, in global memory, gets
-//     A -= (L D) L^T on the matrix cores, in square tiles of Mma::COLS complex
-//     rows and columns (two matrix-core row blocks per tile); a wave keeps one
-//     tile row's A' operands in registers and sweeps that row's tiles, loading
-//     the next tile while the current one is in the matrix pipe; tile rows are
-//     paired (I, T-1-I) across waves for balance.
+// columns per step, NB <= the tile size Mma::COLS.  The NB columns of a step
+// are one contiguous chunk of band storage held in LDS in that layout
+// (Pb[c*ld + d] = entry (k+c+d, k+c)).  Per step:
+//  1. every thread solves one row below the diagonal block, left-looking in
+//     registers: L[r][c] D_c = A[r][c] - sum_{c'<c} L[r][c'] D_c' L[c][c'],
+//     against the diagonal block factored one step earlier;
+//  2. the chunk goes back to global memory (final L and D), and N = -L D of
+//     every trailing row goes to LDS as the matrix-core A' operands;
+//  3. the first tile column of the trailing kd x kd lower triangle gets
+//     A -= (L D) L^T on the matrix cores; its first NB columns are the next
+//     step's chunk and go straight into the (now free) LDS panel, together
+//     with the entries of the next chunk below the trailing window, read from
+//     global memory;
+//  4. wave 0 factors the next chunk's NB x NB diagonal block in registers
+//     (lane r holds row r, column multipliers are broadcast between lanes),
+//     while the other waves, and wave 0 once it is done, update the rest of
+//     the trailing triangle in global memory, one tile row at a time taken
+//     from a shared counter, longest rows first.
+// The update runs in square tiles of Mma::COLS complex rows and columns (two
+// matrix-core row blocks per tile); a wave keeps one tile row's B' operands,
+// L = -N D^{-1}, in registers and sweeps that row's tiles, loading the next
+// tile while the current one is in the matrix pipe.
 // One row of the panel below its diagonal block: x[C] = (x[C] - sum_{c2<C}
 // x[c2] W[C][c2]) D^{-1}_C for C = 0..NB-1, unrolled at compile time so that
 // the row stays in registers.
@@ -287,13 +295,15 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
     constexpr int RB = TS / MM::ROWS;     // matrix-core row blocks per tile (2)
     constexpr int KS = NB / MM::KC;       // matrix-core k steps per tile
     constexpr int QB = 16;                // 16-byte transfers in flight per thread
+    static_assert(NB <= TS, "the next chunk must lie in the first tile column");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int m = st.m, kd = st.n, n_x = m * m, ld = kd + 1;
     cpx<R>* Pb = reinterpret_cast<cpx<R>*>(smem_raw);                 // NB*ld, rounded to units
-    cpx<R>* Dinv = Pb + (NB * ld + CPU - 1) / CPU * CPU;             // NB
-    cpx<R>* W = Dinv + NB;                                            // NB * NB
+    cpx<R>* Dinv = Pb + (NB * ld + CPU - 1) / CPU * CPU;             // 2 * NB (two steps)
+    cpx<R>* W = Dinv + 2 * NB;                                        // NB * NB
     cpx<R>* Xb = W + NB * NB;                                         // 2 * NB
     cpx<R>* Nsw = Xb + 2 * NB;                                        // ceil(kd/TS) * TS * NB
+    int* ctr = reinterpret_cast<int*>(Nsw + (kd + TS - 1) / TS * TS * NB);
     const int l = blockIdx.x;
     cpx<R>* A = band + (size_t)l * band_stride(st);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -305,91 +315,98 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
         const int d = r - c;
         return (d >= 0 && d <= kd) ? Pb[c * ld + d] : zero;
     };
+    // diagonal block of the chunk in Pb (columns k0.., nbk of them), wave 0:
+    // column by column, the pivot by a lane broadcast, L[.][c] published
+    // through LDS (Xb, double-buffered) and read back as broadcasts
+    auto diag = [&](int k0, int nbk, cpx<R>* Dout) {
+        const int r = lane;
+        cpx<R> y[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) y[c] = (r < nbk && c <= r && c < nbk) ? PV(c, r) : zero;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            if (c < nbk) {
+                bool ok;
+                const cpx<R> d = rdlane(y[c], c);
+                const cpx<R> inv = cinv_or_zero(d, ok);
+                if (!ok && bad == 0) bad = k0 + c + 1;
+                const cpx<R> lr = cmul(y[c], inv);          // L[r][c] for r > c
+                cpx<R>* xb = Xb + (c & 1) * NB;
+                if (r < NB) xb[r] = lr;
+                wave_sync();
+#pragma unroll
+                for (int c2 = c + 1; c2 < NB; ++c2)          // Y[r][c2] -= Y[r][c] L[c2][c]
+                    y[c2] = cfms(y[c2], y[c], xb[c2]);
+                if (r > c) y[c] = lr;
+                if (r == c) Dout[c] = inv;
+            }
+        }
+        if (r < nbk) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+                if (c <= r && r - c <= kd) Pb[c * ld + (r - c)] = y[c];
+        }
+    };
+    // ---- first chunk to LDS, its diagonal block
+    {
+        const int units = (min(NB, n_x) * ld + CPU - 1) / CPU;
+        const UT* src = reinterpret_cast<const UT*>(A);
+        UT* dst = reinterpret_cast<UT*>(Pb);
+        for (int base = 0; base < units; base += QB * 256) {
+            UT q[QB];
+#pragma unroll
+            for (int j = 0; j < QB; ++j) {
+                const int e = base + tid + 256 * j;
+                if (e < units) q[j] = src[e];
+            }
+#pragma unroll
+            for (int j = 0; j < QB; ++j) {
+                const int e = base + tid + 256 * j;
+                if (e < units) dst[e] = q[j];
+            }
+        }
+    }
+    lds_barrier();
+    if (wave == 0) diag(0, min(NB, n_x), Dinv);
+    lds_barrier();
+    int par = 0;                                  // Dinv half of the current step
     for (int k = 0; k < n_x; k += NB) {
         const int nb = min(NB, n_x - k);
         const int mrows = min(nb + kd, n_x - k);
-        const int units = (nb * ld + CPU - 1) / CPU;
-        // ---- panel chunk to LDS
-        {
-            const UT* src = reinterpret_cast<const UT*>(A + (size_t)k * ld);
-            UT* dst = reinterpret_cast<UT*>(Pb);
-            for (int base = 0; base < units; base += QB * 256) {
-                UT q[QB];
-#pragma unroll
-                for (int j = 0; j < QB; ++j) {
-                    const int e = base + tid + 256 * j;
-                    if (e < units) q[j] = src[e];
-                }
-#pragma unroll
-                for (int j = 0; j < QB; ++j) {
-                    const int e = base + tid + 256 * j;
-                    if (e < units) dst[e] = q[j];
-                }
-            }
-        }
-        lds_barrier();
-        // ---- 1. diagonal block (wave 0, lane r = row r): column by column,
-        //      the pivot by a lane broadcast, L[.][c] published through LDS
-        //      (Xb, double-buffered) and read back as broadcasts
-        if (wave == 0) {
-            const int r = lane;
-            cpx<R> y[NB];
-#pragma unroll
-            for (int c = 0; c < NB; ++c) y[c] = (r < nb && c <= r && c < nb) ? PV(c, r) : zero;
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                if (c < nb) {
-                    bool ok;
-                    const cpx<R> d = rdlane(y[c], c);
-                    const cpx<R> inv = cinv_or_zero(d, ok);
-                    if (!ok && bad == 0) bad = k + c + 1;
-                    const cpx<R> lr = cmul(y[c], inv);          // L[r][c] for r > c
-                    cpx<R>* xb = Xb + (c & 1) * NB;
-                    if (r < NB) xb[r] = lr;
-                    wave_sync();
-#pragma unroll
-                    for (int c2 = c + 1; c2 < NB; ++c2)          // Y[r][c2] -= Y[r][c] L[c2][c]
-                        y[c2] = cfms(y[c2], y[c], xb[c2]);
-                    if (r > c) y[c] = lr;
-                    if (r == c) Dinv[c] = inv;
-                }
-            }
-            if (r < nb) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c)
-                    if (c <= r && r - c <= kd) Pb[c * ld + (r - c)] = y[c];
-            }
-        }
-        lds_barrier();
-        // ---- 2. rows below the diagonal block, one row per thread in
-        //      registers: L[r][c] = (A[r][c] - sum_{c2<c} L[r][c2] W[c][c2]) / D_c
-        //      with W[c][c2] = D_c2 L[c][c2] from the diagonal block
+        const int ntr = mrows - nb;               // trailing rows/cols
+        const int TT = (ntr + TS - 1) / TS;       // tile rows
+        const int nbn = min(NB, n_x - k - nb);    // width of the next chunk (0 at the end)
+        const cpx<R>* Dk = Dinv + par * NB;
+        cpx<R>* Dn = Dinv + (par ^ 1) * NB;
+        // ---- 1. rows below the diagonal block, one row per thread in
+        //      registers, against W[c][c2] = D_c2 L[c][c2]
         for (int e = tid; e < NB * NB; e += 256) {
             const int c = e / NB, c2 = e - c * NB;
             W[e] = (c2 < c && c < nb) ? cmul(Pb[c2 * ld], Pb[c2 * ld + (c - c2)]) : zero;
         }
+        if (tid == 0) *ctr = 0;
         lds_barrier();
         for (int r = nb + tid; r < mrows; r += 256) {
             cpx<R> x[NB];
 #pragma unroll
             for (int c = 0; c < NB; ++c) x[c] = (c < nb) ? PV(c, r) : zero;
-            row_solve<0, NB>(x, W, Dinv);
+            row_solve<0, NB>(x, W, Dk);
 #pragma unroll
             for (int c = 0; c < NB; ++c)
                 if (c < nb && r - c <= kd) Pb[c * ld + (r - c)] = x[c];
         }
         lds_barrier();
-        // ---- 3. panel chunk back to global memory
+        // ---- 2. chunk back to global memory; A' operands, once for all
+        //      waves: N = -(L D) of every row of the trailing window,
+        //      Nsw[((J*RB + rb)*NB + c)*ROWS + i] for window row
+        //      TS*J + ROWS*rb + i and panel column c
         {
             UT* dst = reinterpret_cast<UT*>(A + (size_t)k * ld);
             const UT* src = reinterpret_cast<const UT*>(Pb);
-            for (int e = tid; e < units; e += 256) dst[e] = src[e];
+            const int full = nb * ld / CPU;
+            for (int e = tid; e < full; e += 256) dst[e] = src[e];
+            if (full * CPU < nb * ld && tid == 0) A[(size_t)k * ld + nb * ld - 1] = Pb[nb * ld - 1];
         }
-        // ---- 4. A' operands, once for all waves: N = -(L D) of every row of
-        //      the trailing window, Nsw[((J*RB + rb)*NB + c)*ROWS + i] for
-        //      window row TS*J + ROWS*rb + i and panel column c
-        const int ntr = mrows - nb;               // trailing rows/cols
-        const int TT = (ntr + TS - 1) / TS;       // tile rows
         for (int e = tid; e < TT * TS * NB; e += 256) {
             const int i = e % MM::ROWS, c = (e / MM::ROWS) % NB, jb = e / (MM::ROWS * NB);
             const int rr = MM::ROWS * jb + i;
@@ -398,29 +415,30 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
             Nsw[e] = cpx<R>{-pv.x, -pv.y};
         }
         lds_barrier();
-        // ---- 5. trailing update on the matrix cores, tile (I, J), J <= I, of
-        //      the lower triangle computed transposed, C^T += N_J L_I^T: a lane
-        //      then owns one row of the tile, and its loads and stores of the
-        //      tile run down the band columns (contiguous).  The 2x2 real block
-        //      of a complex N entry is [[x, -y], [y, x]]; a lane's A' element is
-        //      component a_im ^ a_b of N, negated for (a_im, a_b) = (0, 1).
+        // ---- 3./4. trailing update on the matrix cores, tile (I, J), J <= I,
+        //      of the lower triangle computed transposed, C^T += N_J L_I^T: a
+        //      lane then owns one row of the tile, and its loads and stores of
+        //      the tile run down the band columns (contiguous).  The 2x2 real
+        //      block of a complex N entry is [[x, -y], [y, x]]; a lane's A'
+        //      element is component a_im ^ a_b of N, negated for
+        //      (a_im, a_b) = (0, 1).
         const R* Nf = reinterpret_cast<const R*>(Nsw);
         const int a_off = 2 * (MM::a_k(lane) * MM::ROWS + MM::a_row(lane)) + (MM::a_im(lane) ^ MM::a_b(lane));
         const R a_sgn = (MM::a_b(lane) && !MM::a_im(lane)) ? R(-1) : R(1);
-        const int npairs = (TT + 2 * NW - 1) / (2 * NW);
-        for (int q = 0; q < 2 * npairs; ++q) {
-            const int p = q >> 1;
-            const int I = (q & 1) ? 2 * NW * p + 2 * NW - 1 - wave : 2 * NW * p + wave;
-            if (I >= TT) continue;
-            // B' operands of tile row I: L in real/imaginary parts
+        // tiles J0..J1 of tile row I; head: the first tile column, whose
+        // columns below nbn go to the LDS panel of the next step
+        auto tile_row = [&](int I, int J0, int J1, bool head) {
+            // B' operands of tile row I: L = -N D^{-1}, real/imaginary parts
             R bv[KS];
             {
                 const int rr = TS * I + MM::b_col(lane);
+                const int jb = rr / MM::ROWS, i = rr % MM::ROWS;
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
                     const int c = s * MM::KC + MM::b_k(lane);
-                    const cpx<R> lv = (rr < ntr && c < nb) ? PV(c, nb + rr) : zero;
-                    bv[s] = MM::b_b(lane) ? lv.y : lv.x;
+                    cpx<R> lv = zero;
+                    if (c < nb) lv = cmul(Nsw[(jb * NB + c) * MM::ROWS + i], Dk[c]);
+                    bv[s] = MM::b_b(lane) ? -lv.y : -lv.x;
                 }
             }
             const bool rows_full = TS * (I + 1) <= ntr;
@@ -446,14 +464,26 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
                         for (int e = 0; e < MM::NENT; ++e) {
                             const int cc = TS * J + tcol(rb, e);
                             cpx<R> cv = zero;
-                            if (J <= I && brow < ntr && cc < ntr && brow >= cc) cv = *addr(cc);
+                            if (J <= J1 && brow < ntr && cc < ntr && brow >= cc) cv = *addr(cc);
                             acc[rb][MM::e_re(e)] = cv.x;
                             acc[rb][MM::e_im(e)] = cv.y;
                         }
                 }
             };
             auto store_c = [&](int J, const typename MM::acc_t (&acc)[RB]) {
-                if (J < I && rows_full) {
+                if (head) {
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int e = 0; e < MM::NENT; ++e) {
+                            const int cc = TS * J + tcol(rb, e);
+                            const cpx<R> v = {acc[rb][MM::e_re(e)], acc[rb][MM::e_im(e)]};
+                            if (brow < ntr && cc < ntr && brow >= cc) {
+                                if (cc < nbn) Pb[cc * ld + (brow - cc)] = v;
+                                else *addr(cc) = v;
+                            }
+                        }
+                } else if (J < I && rows_full) {
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -471,9 +501,9 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
                 }
             };
             typename MM::acc_t acc[RB], accn[RB];
-            load_c(0, acc);
-            for (int J = 0; J <= I; ++J) {
-                load_c(J + 1, accn);                 // next tile, in flight during the MFMAs
+            load_c(J0, acc);
+            for (int J = J0; J <= J1; ++J) {
+                if (J < J1) load_c(J + 1, accn);     // next tile, in flight during the MFMAs
 #pragma unroll
                 for (int s = 0; s < KS; ++s)
 #pragma unroll
@@ -485,8 +515,33 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) acc[rb] = accn[rb];
             }
+        };
+        // ---- 3. first tile column -> next chunk; entries of the next chunk
+        //      below the trailing window from global memory
+        for (int I = wave; I < TT; I += NW) tile_row(I, 0, 0, true);
+        if (nbn > 0) {
+            // column c of the next chunk takes rows d >= ntr - c from memory
+            const int fl = min(ld, kd + 1 - ntr + nbn - 1);   // longest such run
+            const cpx<R>* src = A + (size_t)(k + nb) * ld;
+            for (int e = tid; e < nbn * fl; e += 256) {
+                const int c = e / fl, j = e - c * fl;
+                const int d = kd - j;
+                if (d >= ntr - c && d >= 0) Pb[c * ld + d] = src[c * ld + d];
+            }
+        }
+        lds_barrier();
+        // ---- 4. next diagonal block (wave 0) beside the rest of the update
+        if (wave == 0 && nbn > 0) diag(k + nb, nbn, Dn);
+        for (;;) {
+            int t = 0;
+            if (lane == 0) t = atomicAdd(ctr, 1);
+            t = __builtin_amdgcn_readfirstlane(t);
+            const int I = TT - 1 - t;
+            if (I < 1) break;
+            tile_row(I, 1, I, false);
         }
         __syncthreads();
+        par ^= 1;
     }
     if (tid == 0) info[l] = bad;
 }
@@ -1139,13 +1194,14 @@ __global__ void k_fill_int(int* p, int count, int value) {
 }
 
 // LDS of the factorisation: the panel (NB (kd + 1) complex values), D^{-1}
-// and the swizzled B' operands (ceil(kd / TS) tiles x 64 lanes x NB / KC).
+// of two steps, the W table, the column broadcast buffer, the A' operands
+// (ceil(kd / TS) tiles x TS rows x NB) and the tile-row counter.
 template <class R, int NB>
 size_t ldlt_lds_bytes(int kd) {
     constexpr int CPU = Unit<R>::CPU;
-    const size_t panel = (size_t)(NB * (kd + 1) + CPU - 1) / CPU * CPU + NB;
+    const size_t panel = (size_t)(NB * (kd + 1) + CPU - 1) / CPU * CPU + 2 * NB;
     const size_t tiles = (size_t)(kd + Mma<R>::COLS - 1) / Mma<R>::COLS;
-    return (panel + (size_t)NB * NB + 2 * NB + tiles * Mma<R>::COLS * NB) * sizeof(cpx<R>);
+    return (panel + (size_t)NB * NB + 2 * NB + tiles * Mma<R>::COLS * NB) * sizeof(cpx<R>) + 16;
 }
 
 template <class R, int NB>
@@ -1242,7 +1298,8 @@ hipError_t band_fill(int precision, void* band, const double* lambda, int count,
     return hipGetLastError();
 }
 
-// Panel width: the widest of 32, 16, 8 columns whose LDS fits in 150 KiB.
+// Panel width: the widest of 32, 16, 8 columns (at most the tile size) whose
+// LDS fits in 150 KiB.
 hipError_t ldlt_factor(int precision, void* band, int count, const Stencil& st, int* info, hipStream_t s) {
     constexpr size_t cap = 150u * 1024u;
     if (precision == 32) {
@@ -1250,7 +1307,6 @@ hipError_t ldlt_factor(int precision, void* band, int count, const Stencil& st, 
         if (ldlt_lds_bytes<float, 16>(st.n) <= cap) return launch_ldlt<float, 16>(band, count, st, info, s);
         if (ldlt_lds_bytes<float, 8>(st.n) <= cap) return launch_ldlt<float, 8>(band, count, st, info, s);
     } else {
-        if (ldlt_lds_bytes<double, 32>(st.n) <= cap) return launch_ldlt<double, 32>(band, count, st, info, s);
         if (ldlt_lds_bytes<double, 16>(st.n) <= cap) return launch_ldlt<double, 16>(band, count, st, info, s);
         if (ldlt_lds_bytes<double, 8>(st.n) <= cap) return launch_ldlt<double, 8>(band, count, st, info, s);
     }
