@@ -250,51 +250,56 @@ __device__ __forceinline__ void wave_sync() {
 // One workgroup (4 waves) factors one band as L D L^T, right-looking, NB
 // columns per step, NB <= the tile size Mma::COLS.  The NB columns of a step
 // are one contiguous chunk of band storage held in LDS in that layout
-// (Pb[c*ld + d] = entry (k+c+d, k+c)).  Per step:
-//  1. every thread solves one row below the diagonal block, left-looking in
+// (Pb[c*ld + d] = entry (k+c+d, k+c)); its diagonal block was factored one
+// step earlier.  Per step:
+//  1. the W table W[c][c2] = D_c2 L[c][c2] of the diagonal block, which also
+//     goes to global memory (final);
+//  2. every thread solves one row below the diagonal block, left-looking in
 //     registers: L[r][c] D_c = A[r][c] - sum_{c'<c} L[r][c'] D_c' L[c][c'],
-//     against the diagonal block factored one step earlier;
-//  2. the chunk goes back to global memory (final L and D), and N = -L D of
-//     every trailing row goes to LDS as the matrix-core A' operands;
+//     and stores L to global memory (final) and N = -L D to LDS as the
+//     matrix-core A' operands;
 //  3. the first tile column of the trailing kd x kd lower triangle gets
 //     A -= (L D) L^T on the matrix cores; its first NB columns are the next
-//     step's chunk and go straight into the (now free) LDS panel, together
-//     with the entries of the next chunk below the trailing window, read from
-//     global memory;
+//     step's chunk and go straight into the LDS panel, with the entries of
+//     the next chunk below the window;
 //  4. wave 0 factors the next chunk's NB x NB diagonal block in registers
 //     (lane r holds row r, column multipliers are broadcast between lanes),
-//     while the other waves, and wave 0 once it is done, update the rest of
-//     the trailing triangle in global memory, one tile row at a time taken
-//     from a shared counter, longest rows first.
+//     while the other waves, and wave 0 once it is done,
+//     update the rest of the trailing triangle in global memory, one tile row
+//     at a time taken from a shared counter, longest rows first.
 // The update runs in square tiles of Mma::COLS complex rows and columns (two
 // matrix-core row blocks per tile); a wave keeps one tile row's B' operands,
 // L = -N D^{-1}, in registers and sweeps that row's tiles, loading the next
 // tile while the current one is in the matrix pipe.
 // One row of the panel below its diagonal block: x[C] = (x[C] - sum_{c2<C}
 // x[c2] W[C][c2]) D^{-1}_C for C = 0..NB-1, unrolled at compile time so that
-// the row stays in registers.
-template <int C, int NB, class R>
-__device__ __forceinline__ void row_solve(cpx<R> (&x)[NB], const cpx<R>* W, const cpx<R>* Dinv) {
+// the row stays in registers; the value before the scaling, L[r][C] D_C, goes
+// negated to Nrow[C * ROWS].
+template <int C, int NB, int ROWS, class R>
+__device__ __forceinline__ void row_solve(cpx<R> (&x)[NB], const cpx<R>* W, const cpx<R>* Dinv, cpx<R>* Nrow) {
     if constexpr (C < NB) {
 #pragma unroll
         for (int c2 = 0; c2 < C; ++c2) x[C] = cfms(x[C], x[c2], W[C * NB + c2]);
+        Nrow[C * ROWS] = cpx<R>{-x[C].x, -x[C].y};
         x[C] = cmul(x[C], Dinv[C]);
         // finish this column before the next column's table reads, or all
         // NB^2/2 of them would be in registers at once
         __asm__ volatile("" : "+v"(x[C].x), "+v"(x[C].y) : : "memory");
-        row_solve<C + 1, NB>(x, W, Dinv);
+        row_solve<C + 1, NB, ROWS>(x, W, Dinv, Nrow);
     }
 }
 
 template <class R, int NB>
 __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Stencil st, int* __restrict__ info) {
     typedef Mma<R> MM;
+    typedef typename MM::acc_t AT;
     typedef typename Unit<R>::T UT;
     constexpr int CPU = Unit<R>::CPU;
     constexpr int TS = MM::COLS;          // tile size (complex rows = cols)
     constexpr int RB = TS / MM::ROWS;     // matrix-core row blocks per tile (2)
     constexpr int KS = NB / MM::KC;       // matrix-core k steps per tile
     constexpr int QB = 16;                // 16-byte transfers in flight per thread
+    constexpr int NW = 4;                 // waves
     static_assert(NB <= TS, "the next chunk must lie in the first tile column");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int m = st.m, kd = st.n, n_x = m * m, ld = kd + 1;
@@ -307,7 +312,6 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
     const int l = blockIdx.x;
     cpx<R>* A = band + (size_t)l * band_stride(st);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NW = 4;
     const cpx<R> zero = {R(0), R(0)};
     int bad = 0;
     // entry (row r, column c) of the panel, relative to the step start
@@ -369,6 +373,12 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
     lds_barrier();
     if (wave == 0) diag(0, min(NB, n_x), Dinv);
     lds_barrier();
+    // matrix-core operands: the 2x2 real block of a complex N entry is
+    // [[x, -y], [y, x]]; a lane's A' element is component a_im ^ a_b of N,
+    // negated for (a_im, a_b) = (0, 1)
+    const R* Nf = reinterpret_cast<const R*>(Nsw);
+    const int a_off = 2 * (MM::a_k(lane) * MM::ROWS + MM::a_row(lane)) + (MM::a_im(lane) ^ MM::a_b(lane));
+    const R a_sgn = (MM::a_b(lane) && !MM::a_im(lane)) ? R(-1) : R(1);
     int par = 0;                                  // Dinv half of the current step
     for (int k = 0; k < n_x; k += NB) {
         const int nb = min(NB, n_x - k);
@@ -378,53 +388,10 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
         const int nbn = min(NB, n_x - k - nb);    // width of the next chunk (0 at the end)
         const cpx<R>* Dk = Dinv + par * NB;
         cpx<R>* Dn = Dinv + (par ^ 1) * NB;
-        // ---- 1. rows below the diagonal block, one row per thread in
-        //      registers, against W[c][c2] = D_c2 L[c][c2]
-        for (int e = tid; e < NB * NB; e += 256) {
-            const int c = e / NB, c2 = e - c * NB;
-            W[e] = (c2 < c && c < nb) ? cmul(Pb[c2 * ld], Pb[c2 * ld + (c - c2)]) : zero;
-        }
-        if (tid == 0) *ctr = 0;
-        lds_barrier();
-        for (int r = nb + tid; r < mrows; r += 256) {
-            cpx<R> x[NB];
-#pragma unroll
-            for (int c = 0; c < NB; ++c) x[c] = (c < nb) ? PV(c, r) : zero;
-            row_solve<0, NB>(x, W, Dk);
-#pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c < nb && r - c <= kd) Pb[c * ld + (r - c)] = x[c];
-        }
-        lds_barrier();
-        // ---- 2. chunk back to global memory; A' operands, once for all
-        //      waves: N = -(L D) of every row of the trailing window,
-        //      Nsw[((J*RB + rb)*NB + c)*ROWS + i] for window row
-        //      TS*J + ROWS*rb + i and panel column c
-        {
-            UT* dst = reinterpret_cast<UT*>(A + (size_t)k * ld);
-            const UT* src = reinterpret_cast<const UT*>(Pb);
-            const int full = nb * ld / CPU;
-            for (int e = tid; e < full; e += 256) dst[e] = src[e];
-            if (full * CPU < nb * ld && tid == 0) A[(size_t)k * ld + nb * ld - 1] = Pb[nb * ld - 1];
-        }
-        for (int e = tid; e < TT * TS * NB; e += 256) {
-            const int i = e % MM::ROWS, c = (e / MM::ROWS) % NB, jb = e / (MM::ROWS * NB);
-            const int rr = MM::ROWS * jb + i;
-            cpx<R> pv = zero;
-            if (rr < ntr && c < nb) pv = cmul(Pb[c * ld], PV(c, nb + rr));
-            Nsw[e] = cpx<R>{-pv.x, -pv.y};
-        }
-        lds_barrier();
-        // ---- 3./4. trailing update on the matrix cores, tile (I, J), J <= I,
-        //      of the lower triangle computed transposed, C^T += N_J L_I^T: a
-        //      lane then owns one row of the tile, and its loads and stores of
-        //      the tile run down the band columns (contiguous).  The 2x2 real
-        //      block of a complex N entry is [[x, -y], [y, x]]; a lane's A'
-        //      element is component a_im ^ a_b of N, negated for
-        //      (a_im, a_b) = (0, 1).
-        const R* Nf = reinterpret_cast<const R*>(Nsw);
-        const int a_off = 2 * (MM::a_k(lane) * MM::ROWS + MM::a_row(lane)) + (MM::a_im(lane) ^ MM::a_b(lane));
-        const R a_sgn = (MM::a_b(lane) && !MM::a_im(lane)) ? R(-1) : R(1);
+        // The trailing update, tile (I, J), J <= I, of the lower triangle
+        // computed transposed, C^T += N_J L_I^T: a lane owns one row of the
+        // tile (window row TS I + c_col), and its loads and stores of the tile
+        // run down the band columns (contiguous).
         // tiles J0..J1 of tile row I; head: the first tile column, whose
         // columns below nbn go to the LDS panel of the next step
         auto tile_row = [&](int I, int J0, int J1, bool head) {
@@ -516,18 +483,42 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
                 for (int rb = 0; rb < RB; ++rb) acc[rb] = accn[rb];
             }
         };
-        // ---- 3. first tile column -> next chunk; entries of the next chunk
-        //      below the trailing window from global memory
+        // ---- 1. W table, the diagonal block to global memory (final); A'
+        //      operands of rows past the window are zero
+        for (int e = tid; e < NB * NB; e += 256) {
+            const int c = e / NB, c2 = e - c * NB;
+            W[e] = (c2 < c && c < nb) ? cmul(Pb[c2 * ld], Pb[c2 * ld + (c - c2)]) : zero;
+            // entry (k + c + c2, k + c) of the block
+            if (c < nb && c + c2 < nb && c2 <= kd) A[(size_t)(k + c) * ld + c2] = Pb[c * ld + c2];
+        }
+        for (int e = tid; e < (TT * TS - ntr) * NB; e += 256) {
+            const int rr = ntr + e / NB, c = e % NB;
+            Nsw[(rr / MM::ROWS * NB + c) * MM::ROWS + rr % MM::ROWS] = zero;
+        }
+        if (tid == 0) *ctr = 0;
+        lds_barrier();
+        // ---- 2. rows below the diagonal block
+        for (int r = nb + tid; r < mrows; r += 256) {
+            cpx<R> x[NB];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) x[c] = (c < nb) ? PV(c, r) : zero;
+            const int rr = r - nb;
+            row_solve<0, NB, MM::ROWS>(x, W, Dk, Nsw + (rr / MM::ROWS) * NB * MM::ROWS + rr % MM::ROWS);
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+                if (c < nb && r - c <= kd) A[(size_t)(k + c) * ld + (r - c)] = x[c];
+        }
+        lds_barrier();
+        // ---- 3. first tile column -> next chunk; the next chunk's entries
+        //      below the window from global memory (column c takes rows
+        //      d >= ntr - c)
         for (int I = wave; I < TT; I += NW) tile_row(I, 0, 0, true);
-        if (nbn > 0) {
-            // column c of the next chunk takes rows d >= ntr - c from memory
-            const int fl = min(ld, kd + 1 - ntr + nbn - 1);   // longest such run
-            const cpx<R>* src = A + (size_t)(k + nb) * ld;
-            for (int e = tid; e < nbn * fl; e += 256) {
-                const int c = e / fl, j = e - c * fl;
-                const int d = kd - j;
-                if (d >= ntr - c && d >= 0) Pb[c * ld + d] = src[c * ld + d];
-            }
+        const int fl = min(ld, kd + 1 - ntr + nbn - 1);   // longest such run
+        const int nfresh = nbn > 0 ? nbn * fl : 0;
+        const cpx<R>* fsrc = A + (size_t)(k + nb) * ld;
+        for (int e = tid; e < nfresh; e += 256) {
+            const int c = e / fl, d = kd - (e - c * fl);
+            if (d >= ntr - c) Pb[c * ld + d] = fsrc[c * ld + d];
         }
         lds_barrier();
         // ---- 4. next diagonal block (wave 0) beside the rest of the update
