@@ -430,8 +430,11 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
 #pragma unroll
                         for (int e = 0; e < MM::NENT; ++e) {
                             const int cc = TS * J + tcol(rb, e);
-                            cpx<R> cv = zero;
-                            if (J <= J1 && brow < ntr && cc < ntr && brow >= cc) cv = *addr(cc);
+                            // unconditional load from a valid address (window
+                            // entry (0, 0) stands in), zero selected after
+                            const bool in = J <= J1 && brow < ntr && cc < ntr && brow >= cc;
+                            const cpx<R> lv = *(in ? addr(cc) : A + (size_t)(k + nb) * ld);
+                            const cpx<R> cv = in ? lv : zero;
                             acc[rb][MM::e_re(e)] = cv.x;
                             acc[rb][MM::e_im(e)] = cv.y;
                         }
@@ -467,10 +470,14 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
                         }
                 }
             };
-            typename MM::acc_t acc[RB], accn[RB];
-            load_c(J0, acc);
-            for (int J = J0; J <= J1; ++J) {
-                if (J < J1) load_c(J + 1, accn);     // next tile, in flight during the MFMAs
+            // The product of a tile is formed from zero and added to the tile
+            // just before its store, so that the tile's loads only have to
+            // land by then; two tile buffers take turns, the next tile's loads
+            // in flight during the current tile's MFMAs.
+            auto update = [&](int J, const typename MM::acc_t (&c)[RB]) {
+                typename MM::acc_t acc[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) acc[rb] = typename MM::acc_t{};
 #pragma unroll
                 for (int s = 0; s < KS; ++s)
 #pragma unroll
@@ -478,9 +485,18 @@ __global__ __launch_bounds__(256, 1) void k_ldlt(cpx<R>* __restrict__ band, Sten
                         const R av = a_sgn * Nf[((J * RB + rb) * NB + s * MM::KC) * MM::ROWS * 2 + a_off];
                         acc[rb] = MM::mma(av, bv[s], acc[rb]);
                     }
-                store_c(J, acc);
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) acc[rb] = accn[rb];
+                for (int rb = 0; rb < RB; ++rb) acc[rb] += c[rb];
+                store_c(J, acc);
+            };
+            typename MM::acc_t ta[RB], tb[RB];
+            load_c(J0, ta);
+            for (int J = J0; J <= J1; J += 2) {
+                if (J < J1) load_c(J + 1, tb);
+                update(J, ta);
+                if (J == J1) break;
+                if (J + 1 < J1) load_c(J + 2, ta);
+                update(J + 1, tb);
             }
         };
         // ---- 1. W table, the diagonal block to global memory (final); A'
