@@ -273,13 +273,18 @@ __device__ __forceinline__ void wave_sync() {
 // tile while the current one is in the matrix pipe.
 // One row of the panel below its diagonal block: x[C] = (x[C] - sum_{c2<C}
 // x[c2] W[C][c2]) D^{-1}_C for C = 0..NB-1, unrolled at compile time so that
-// the row stays in registers; the value before the scaling, L[r][C] D_C, goes
-// negated to Nrow[C * ROWS].
+// the row stays in registers; the sum is formed on its own and subtracted
+// once (fewer roundings at the entry's magnitude).  The value before the
+// scaling, L[r][C] D_C, goes negated to Nrow[C * ROWS].
 template <int C, int NB, int ROWS, class R>
 __device__ __forceinline__ void row_solve(cpx<R> (&x)[NB], const cpx<R>* W, const cpx<R>* Dinv, cpx<R>* Nrow) {
     if constexpr (C < NB) {
+        if constexpr (C > 0) {
+            cpx<R> sum = {R(0), R(0)};
 #pragma unroll
-        for (int c2 = 0; c2 < C; ++c2) x[C] = cfms(x[C], x[c2], W[C * NB + c2]);
+            for (int c2 = 0; c2 < C; ++c2) sum = cfma(x[c2], W[C * NB + c2], sum);
+            x[C] = csub(x[C], sum);
+        }
         Nrow[C * ROWS] = cpx<R>{-x[C].x, -x[C].y};
         x[C] = cmul(x[C], Dinv[C]);
         // finish this column before the next column's table reads, or all
