@@ -86,6 +86,33 @@ def run_steps(st, torch, inputs, precision, steps, warmup, tol, max_iter, refine
     return (t1 - t0) * 1000.0 / steps, reports, Psi
 
 
+def reuse_rates(st, torch, inputs, precision, steps, tol, max_iter, refine):
+    """Solve-only and adjoint rates with the factors reused: one fdm_factor,
+    then `steps` forward and `steps` adjoint solves (refinement included), each
+    after one untimed call."""
+    Mt, Bt, Ms, As, n, F = inputs
+    h = st.fdm_factor(Mt, Bt, Ms, As, n, precision=precision, tol=tol, max_iter=max_iter, refine=refine)
+    out = {}
+    try:
+        for name, fn in (("solve", h.solve), ("adjoint", h.solve_adjoint)):
+            fn(F)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = []
+            for _ in range(steps):
+                fn(F)
+                reps.append(dict(h.last_report))
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1000.0 / steps
+            out[name] = {"ms": ms, "iterations": [r["iterations"] for r in reps],
+                         "rel_residual": [r["rel_residual"] for r in reps]}
+            progress("fp%d %s only: %.1f ms, %d extra applications of the inverse"
+                     % (precision, name, ms, reps[-1]["iterations"]))
+    finally:
+        h.close()
+    return out
+
+
 def cpu_baseline(wl, Mt, Bt, F_np, stride):
     from oracle import baseline
     _, t = baseline.fdm_timed(Mt, Bt, wl.n, F_np, block_stride=stride)
@@ -181,6 +208,8 @@ def main():
                             "history": reps32[-1]["history"]},
         "kappa_x": reps32[-1]["kappa_x"],
     }
+    reuse = reuse_rates(st, torch, inputs, 32, args.steps, args.tol, args.max_iter, args.refine)
+    out["reused_factors_fp32"] = {name: dict(r, dof_per_s=wl.dofs / (r["ms"] / 1000.0)) for name, r in reuse.items()}
     if not args.no_fp64:
         ms64, reps64, _ = run_steps(st, torch, inputs, 64, args.steps, args.warmup, args.tol, args.max_iter, "gmres")
         v64 = wl.dofs / (ms64 / 1000.0)
