@@ -120,34 +120,6 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// ------------------------------------------------------------------ band fill
-template <class R>
-__global__ __launch_bounds__(256) void k_band_fill(cpx<R>* __restrict__ band, const double* __restrict__ lam,
-                                                   Stencil st) {
-    const int l = blockIdx.y;
-    const double lr = lam[2 * l], li = lam[2 * l + 1];
-    const int m = st.m, ld = st.n + 1;
-    const long long per = (long long)st.m * st.m * (st.n + 1);
-    cpx<R>* B = band + (size_t)l * band_stride(st);
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < per;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int j = (int)(e / ld), d = (int)(e - (long long)j * ld);
-        const int jx = j % m, jy = j / m;
-        int q = -1;
-        if (d == 0)
-            q = STFEM_ST_C;
-        else if (d == 1 && jx < m - 1)
-            q = STFEM_ST_E;
-        else if (d == m && jy < m - 1)
-            q = STFEM_ST_N;
-        else if (d == m + 1 && jx < m - 1 && jy < m - 1)
-            q = STFEM_ST_NE;
-        cpx<R> v = {R(0), R(0)};
-        if (q >= 0) v = {(R)(lr * st.M[q] + st.A[q]), (R)(li * st.M[q])};
-        B[e] = v;
-    }
-}
-
 __device__ __forceinline__ float rdlane(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
@@ -176,6 +148,72 @@ struct Unit<double> {
     typedef f64x2 T;
     static constexpr int CPU = 1;
 };
+// ------------------------------------------------------------------ band fill
+// Entries of S_l = lambda_l M + A in the lower band: C on the diagonal, E
+// (d = 1, not at the right end of a grid row), N (d = m, not in the top grid
+// row) and NE (d = m + 1, neither); everything else, including rows beyond
+// the matrix, is zero.  A thread writes the 16-byte units t, t + 256, ... of
+// its block's chunk and follows (column j, offset d) incrementally instead of
+// dividing per entry.
+constexpr int FILL_UPT = 8;   // 16-byte units per thread and chunk
+template <class R>
+__global__ __launch_bounds__(256) void k_band_fill(cpx<R>* __restrict__ band, const double* __restrict__ lam,
+                                                   Stencil st) {
+    typedef typename Unit<R>::T UT;
+    constexpr int CPU = Unit<R>::CPU;
+    const int l = blockIdx.y;
+    const double lr = lam[2 * l], li = lam[2 * l + 1];
+    const int m = st.m, ld = st.n + 1;
+    const cpx<R> vC = {(R)(lr * st.M[STFEM_ST_C] + st.A[STFEM_ST_C]), (R)(li * st.M[STFEM_ST_C])};
+    const cpx<R> vE = {(R)(lr * st.M[STFEM_ST_E] + st.A[STFEM_ST_E]), (R)(li * st.M[STFEM_ST_E])};
+    const cpx<R> vN = {(R)(lr * st.M[STFEM_ST_N] + st.A[STFEM_ST_N]), (R)(li * st.M[STFEM_ST_N])};
+    const cpx<R> vNE = {(R)(lr * st.M[STFEM_ST_NE] + st.A[STFEM_ST_NE]), (R)(li * st.M[STFEM_ST_NE])};
+    auto val = [=](int d, int jx, int jy) -> cpx<R> {
+        const bool e = d == 1 && jx < m - 1, n = d == m && jy < m - 1;
+        const bool ne = d == m + 1 && jx < m - 1 && jy < m - 1;
+        R x = d == 0 ? vC.x : R(0), y = d == 0 ? vC.y : R(0);
+        x = e ? vE.x : x;
+        y = e ? vE.y : y;
+        x = n ? vN.x : x;
+        y = n ? vN.y : y;
+        x = ne ? vNE.x : x;
+        y = ne ? vNE.y : y;
+        return cpx<R>{x, y};
+    };
+    const long long per = (long long)m * m * ld;                 // entries of one block
+    const long long units = (per + CPU - 1) / CPU;               // the last may run into the padding
+    UT* B = reinterpret_cast<UT*>(band + (size_t)l * band_stride(st));
+    const long long chunk = 256LL * FILL_UPT;
+    for (long long base = (long long)blockIdx.x * chunk; base < units; base += (long long)gridDim.x * chunk) {
+        const long long e0 = (base + threadIdx.x) * CPU;         // first entry of the thread's first unit
+        int j = (int)(e0 / ld), d = (int)(e0 - (long long)j * ld);
+        int jx = j % m, jy = j / m;
+#pragma unroll
+        for (int i = 0; i < FILL_UPT; ++i) {
+            const long long u = base + threadIdx.x + 256LL * i;
+            if (u < units) {
+                const cpx<R> v0 = val(d, jx, jy);
+                if constexpr (CPU == 2) {
+                    // the unit's second entry, possibly the next column's first
+                    const bool wrap = d + 1 == ld;
+                    const int jx1 = wrap ? (jx + 1 == m ? 0 : jx + 1) : jx;
+                    const int jy1 = wrap ? (jx + 1 == m ? jy + 1 : jy) : jy;
+                    const cpx<R> v1 = val(wrap ? 0 : d + 1, jx1, jy1);
+                    B[u] = UT{v0.x, v0.y, v1.x, v1.y};
+                } else {
+                    B[u] = UT{v0.x, v0.y};
+                }
+            }
+            // advance by 256 units
+            d += 256 * CPU;
+            while (d >= ld) {
+                d -= ld;
+                if (++jx == m) { jx = 0; ++jy; }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------- LDL^T
 // Matrix-core shapes.  A complex product C += P Q is computed as the real
 // product C' += A' B': every complex row of C is a real row pair (Re, Im) of
@@ -1301,8 +1339,8 @@ hipError_t launch_sweep(const void* band, int count, const Stencil& st, const do
 
 hipError_t band_fill(int precision, void* band, const double* lambda, int count, const Stencil& st, hipStream_t s) {
     const long long per = (long long)st.m * st.m * (st.n + 1);
-    const int bx = (int)std::min<long long>((per + 255) / 256, 2048);
-    (void)per;
+    const long long units = precision == 32 ? (per + 1) / 2 : per;
+    const int bx = (int)std::min<long long>((units + 256LL * FILL_UPT - 1) / (256LL * FILL_UPT), 1024);
     if (precision == 32)
         hipLaunchKernelGGL(k_band_fill<float>, dim3(bx, count), dim3(256), 0, s, (cpx<float>*)band, lambda, st);
     else
