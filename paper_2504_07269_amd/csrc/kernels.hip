@@ -691,6 +691,13 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
             Y[rh * Sz + (i & msk)] = {(R)v.x, (R)v.y};
         }
     }
+    // rows of g that enter the window, loaded one step before they are
+    // stored (threads t1 < NB * NR of waves 1-4): row kd + t1 % NB at step 0
+    double2 gq = make_double2(0.0, 0.0);
+    if (!producer && wave > 0 && t1 < NB * NR) {
+        const int rh = t1 / NB, i = kd + (t1 % NB);
+        if (i < n_x) gq = g[(size_t)rh * rstride + i];
+    }
     lds_barrier();
     for (int p = 0; p < npanel; ++p) {
         const int k = p * NB, nb = min(NB, n_x - k), kp = k - NB;
@@ -750,8 +757,11 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
                         const int rr = i - kp;                // row offset in panel p-1
                         cpx<R> acc = cz;
 #pragma unroll
-                        for (int c = 0; c < NB; ++c)
-                            if (rr - c <= kd) acc = cfma(PV(slotq, c, rr), yq[c], acc);
+                        for (int c = 0; c < NB; ++c) {
+                            // in the slot for every c (rr < NB + kd); zero past the band
+                            const cpx<R> lv = PV(slotq, c, rr);
+                            acc = cfma(rr - c <= kd ? lv : cz, yq[c], acc);
+                        }
                         cpx<R>& yi = Y[i & msk];
                         yi = csub(yi, acc);
                     }
@@ -780,10 +790,8 @@ __global__ __launch_bounds__(512, 1) void k_sweep(const cpx<R>* __restrict__ ban
             }
             if (t1 < NB * NR) {                               // rows first reached at step p+1
                 const int rh = t1 / NB, i = k + kd + (t1 % NB);
-                if (i < n_x) {
-                    const double2 v = g[(size_t)rh * rstride + i];
-                    Y[rh * Sz + (i & msk)] = {(R)v.x, (R)v.y};
-                }
+                if (i < n_x) Y[rh * Sz + (i & msk)] = {(R)gq.x, (R)gq.y};
+                if (i + NB < n_x) gq = g[(size_t)rh * rstride + i + NB];   // for the next step
             }
         }
         lds_barrier();
