@@ -40,7 +40,9 @@ def _case(n, count, seed, im_min):
 
 
 @pytest.mark.parametrize("precision", [64, 32])
-@pytest.mark.parametrize("n,count,nrhs", [(2, 3, 1), (3, 5, 2), (7, 6, 3), (16, 16, 5), (21, 4, 1)])
+# n = 40 (kd = 40) puts the panel width below kd with a partial last tile row
+# of the trailing window (FP32: 32 + 8 rows, FP64: 16 + 16 + 8 rows)
+@pytest.mark.parametrize("n,count,nrhs", [(2, 3, 1), (3, 5, 2), (7, 6, 3), (16, 16, 5), (21, 4, 1), (40, 2, 2)])
 def test_factor_and_solve_match_oracle(precision, n, count, nrhs):
     Ms, As, n_x, kd, Mx, Ax, lam = _case(n, count, 100 + n, 1e-2)
     G = synth.random_rhs(7 + n, count, n_x, nrhs)
