@@ -290,8 +290,8 @@ __device__ __forceinline__ void wave_sync() {
 // are one contiguous chunk of band storage held in LDS in that layout
 // (Pb[c*ld + d] = entry (k+c+d, k+c)); its diagonal block was factored one
 // step earlier.  Per step:
-//  1. the W table W[c][c2] = D_c2 L[c][c2] of the diagonal block, which also
-//     goes to global memory (final);
+//  1. the W table W[c][c2] = D_c2 L[c][c2] of the diagonal block; the block
+//     itself goes to global memory (final);
 //  2. every thread solves one row below the diagonal block, left-looking in
 //     registers: L[r][c] D_c = A[r][c] - sum_{c'<c} L[r][c'] D_c' L[c][c'],
 //     and stores L to global memory (final) and N = -L D to LDS as the
@@ -307,8 +307,10 @@ __device__ __forceinline__ void wave_sync() {
 //     at a time taken from a shared counter, longest rows first.
 // The update runs in square tiles of Mma::COLS complex rows and columns (two
 // matrix-core row blocks per tile); a wave keeps one tile row's B' operands,
-// L = -N D^{-1}, in registers and sweeps that row's tiles, loading the next
-// tile while the current one is in the matrix pipe.
+// L = -N D^{-1}, in registers and sweeps that row's tiles.  Each tile's
+// product is formed from zero and added to the tile just before its store;
+// two tile buffers take turns, the next tile's loads in flight during the
+// current tile's MFMAs.
 // One row of the panel below its diagonal block: x[C] = (x[C] - sum_{c2<C}
 // x[c2] W[C][c2]) D^{-1}_C for C = 0..NB-1, unrolled at compile time so that
 // the row stays in registers; the sum is formed on its own and subtracted
@@ -614,7 +616,8 @@ constexpr int SWEEP_PROD = 192;    // threads of waves 5-7
 //                    the NB rows of panel p and solves their unit triangle
 //                    (register broadcasts between lanes); waves 1-4 subtract
 //                    the contributions of panel p-1 from the kd - NB rows
-//                    below panel p and fetch the NB rows of g that enter;
+//                    below panel p and store the NB rows of g that enter
+//                    (loaded one step earlier);
 //  backward, step b  (panel p = last - b) wave 0 forms the dot products of the
 //                    columns of panel p with the x of panel p+1, adds the far
 //                    sums prepared one step earlier and solves the transposed
