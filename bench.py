@@ -132,7 +132,7 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=60)
-    ap.add_argument("--refine", default="gmres", choices=["gmres", "plain"],
+    ap.add_argument("--refine", default="gmres", choices=["gmres", "plain", "block"],
                     help="refinement of the FP32 solve (the FP64 comparison always uses gmres)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -196,7 +196,8 @@ def main():
                                "on (0,%g) (n_t=%d), %d space-time dofs, 1 rhs, manufactured psi omega=%.4g, "
                                "FP32 LDL^T + FP64 %s refinement to %.0e"
                                % (wl.n, n_x, kd, wl.N_t, wl.p_t, wl.T, wl.n_t, wl.dofs, wl.omega,
-                                  "GMRES" if args.refine == "gmres" else "plain", args.tol),
+                                  {"gmres": "GMRES", "plain": "plain", "block": "block GMRES"}[args.refine],
+                                  args.tol),
                    "dofs": wl.dofs, "n_x": n_x, "n_t": wl.n_t, "rhs": 1},
         "roofline": {"kernel": "k_ldlt (FP32)", "bound": "mfma", "achieved": achieved,
                      "peak": MFMA_PEAK_TFLOPS[32], "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS[32],

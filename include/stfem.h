@@ -72,11 +72,18 @@ enum { STFEM_ST_C = 0, STFEM_ST_E, STFEM_ST_W, STFEM_ST_N, STFEM_ST_S, STFEM_ST_
  *    with classical Gram-Schmidt applied twice; each cycle ends with a
  *    recomputed residual;
  *  - STFEM_REFINE_PLAIN: classical iterative refinement,
- *    Psi <- Psi + FDM^{-1} (F - K Psi).
+ *    Psi <- Psi + FDM^{-1} (F - K Psi);
+ *  - STFEM_REFINE_BLOCK: GMRES on every block system S_l u_l = g_l in the
+ *    eigen-coordinates g = W F (Sec. 3: K = (M_t X (x) I) blockdiag(S_l)
+ *    (X^{-1} (x) I), so the transformed operator is block diagonal), with
+ *    FP64 block residuals and one forward and one back transform per round;
+ *    each block is driven to tol ||F|| / (||M_t X||_2 sqrt(n_t)) (adjoint:
+ *    ||X^{-1}||_2), the global residual is then checked, and at most three
+ *    rounds run.  This is how chunked factors are always refined.
  * GMRES contracts much faster when a few spatial blocks are ill conditioned
  * in FP32, because their error lives in a few directions that the Krylov
  * space removes. */
-enum { STFEM_REFINE_GMRES = 0, STFEM_REFINE_PLAIN = 1 };
+enum { STFEM_REFINE_GMRES = 0, STFEM_REFINE_PLAIN = 1, STFEM_REFINE_BLOCK = 2 };
 
 typedef struct stfem_options {
     int precision;      /* 32: complex FP32 factors and sweeps, FP64 refinement;
@@ -84,7 +91,7 @@ typedef struct stfem_options {
     int max_iter;       /* applications of the FDM inverse beyond the first (>= 0) */
     double tol;         /* target ||F - K Psi||_2 / ||F||_2, per right-hand side;
                            <= 0 disables the residual check (single pass)          */
-    int refine;         /* STFEM_REFINE_GMRES (0, default) or STFEM_REFINE_PLAIN   */
+    int refine;         /* STFEM_REFINE_GMRES (0, default), _PLAIN or _BLOCK       */
     int restart;        /* GMRES: applications of the inverse per cycle before a
                            restart; 0 = automatic (1 + max_iter, at most 23)       */
     double factor_budget; /* bytes of device memory for factor storage; 0 = the

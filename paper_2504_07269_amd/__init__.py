@@ -81,7 +81,7 @@ def fdm_temporal(M_t, B_t):
 class FDM:
     """Owner of a factored Kronecker system (stfem_handle)."""
 
-    REFINE = {"gmres": 0, "plain": 1}
+    REFINE = {"gmres": 0, "plain": 1, "block": 2}
 
     def __init__(self, M_t, B_t, M_st, A_st, n, precision=64, tol=1e-10, max_iter=30, stream=None, refine="gmres",
                  restart=0, factor_budget=0.0):

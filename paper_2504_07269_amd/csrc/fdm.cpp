@@ -142,7 +142,7 @@ struct CachedBuffer {
 std::mutex g_cache_mutex;
 std::vector<CachedBuffer> g_cache;
 constexpr size_t CACHE_MIN_BYTES = (size_t)64 << 20;
-constexpr int CACHE_PER_DEVICE = 6;
+constexpr int CACHE_PER_DEVICE = 12;
 
 void release_cache_locked() {
     for (auto& c : g_cache) (void)hipFree(c.ptr);
@@ -698,7 +698,8 @@ double spectral_norm(int n, F1 apply, F2 apply_h) {
 }
 
 // Solve with the factors computed chunk by chunk (the factors of all n_t
-// blocks exceed the budget).  The transformed rhs G = W F (adjoint: X^H F) is
+// blocks exceed the budget), or with resident factors as one chunk when the
+// block refinement is chosen.  The transformed rhs G = W F (adjoint: X^H F) is
 // formed once; then per chunk of eigen-indices: band fill + LDL^T of its
 // blocks, and GMRES on each block system S_l u_l = g_l (adjoint: conj(S_l))
 // preconditioned by the chunk's factors, with FP64 block residuals, to
@@ -845,8 +846,10 @@ int solve_chunked(stfem_handle* h, const double* F, double* Psi, int nrhs, int a
         if (rel <= tol || !std::isfinite(rel)) break;
         rhs = h->R_ws;
     }
-    b->ms_fill = ms_fill;
-    b->ms_ldlt = ms_ldlt;
+    if (h->nchunks > 1) {   // resident factors keep their factorisation times
+        b->ms_fill = ms_fill;
+        b->ms_ldlt = ms_ldlt;
+    }
     return STFEM_OK;
 }
 
@@ -866,7 +869,7 @@ int solve_common(stfem_handle* h, const void* F_dev, void* Psi_dev, int nrhs, vo
     double rel = -1.0;
     double hist[16];
     for (double& x : hist) x = -1.0;
-    if (h->nchunks > 1) {
+    if (h->nchunks > 1 || (h->opt.tol > 0 && h->opt.refine == STFEM_REFINE_BLOCK)) {
         int applied = 0;
         st = solve_chunked(h, F, Psi, nrhs, adjoint, s, applied, rel, hist);
         if (st) return st;
@@ -995,8 +998,8 @@ extern "C" int fdm_factor(const double* M_t, const double* B_t, int n_t, const d
     if (opt) o = *opt;
     if (o.precision != 32 && o.precision != 64) return fail(STFEM_EINVAL, "fdm_factor: precision must be 32 or 64");
     if (o.max_iter < 0) return fail(STFEM_EINVAL, "fdm_factor: max_iter must be >= 0");
-    if (o.refine != STFEM_REFINE_GMRES && o.refine != STFEM_REFINE_PLAIN)
-        return fail(STFEM_EINVAL, "fdm_factor: refine must be STFEM_REFINE_GMRES or STFEM_REFINE_PLAIN");
+    if (o.refine != STFEM_REFINE_GMRES && o.refine != STFEM_REFINE_PLAIN && o.refine != STFEM_REFINE_BLOCK)
+        return fail(STFEM_EINVAL, "fdm_factor: refine must be STFEM_REFINE_GMRES, _PLAIN or _BLOCK");
     if (o.restart < 0) return fail(STFEM_EINVAL, "fdm_factor: restart must be >= 0");
     if (!(o.factor_budget >= 0)) return fail(STFEM_EINVAL, "fdm_factor: factor_budget must be >= 0");
     if (n < 2 || n > 1024) return fail(STFEM_EINVAL, "fdm_factor: need 2 <= n <= 1024");
@@ -1077,7 +1080,7 @@ extern "C" int fdm_factor(const double* M_t, const double* B_t, int n_t, const d
         hipMemcpyAsync(h->tM_dev, tM.data(), tM.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(h->tB_dev, tB.data(), tB.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
         return cleanup(fail(STFEM_EHIP, "fdm_factor: upload failed"));
-    if (h->nchunks > 1) {
+    if (h->nchunks > 1 || o.refine == STFEM_REFINE_BLOCK) {
         // ||M_t X||_2 and ||X^{-1}||_2 = ||W M_t||_2 for the block tolerances
         const std::vector<cplx>& X = h->dec.X;
         const std::vector<cplx>& W = h->dec.W;
@@ -1105,9 +1108,11 @@ extern "C" int fdm_factor(const double* M_t, const double* B_t, int n_t, const d
             n_t, [&](const std::vector<cplx>& v, std::vector<cplx>& y) { mt(v, tmp); mul(W, false, tmp, y); },
             [&](const std::vector<cplx>& v, std::vector<cplx>& y) { mul(W, true, v, tmp); mt(tmp, y); });
         HIPCHECK(hipStreamSynchronize(s));
-    } else {
+    }
+    if (h->nchunks == 1) {
         st = blocks_finish(h->blk, s);
         if (st) return cleanup(st);
+        h->blk->factored = true;
     }
     h->ms_factor = now_ms() - t1;
     *out = h;

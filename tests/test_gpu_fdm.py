@@ -38,7 +38,7 @@ def oracle_rhs_c0(n=16, N_t=16, T=1.0, p=1):
     return solvers.lift_constant(F, psi0, Mf, Ax)
 
 
-@pytest.mark.parametrize("refine", ["gmres", "plain"])
+@pytest.mark.parametrize("refine", ["gmres", "plain", "block"])
 @pytest.mark.parametrize("precision,tol", [(64, 1e-13), (32, 1e-12)])
 def test_c0_matches_dense_global_lu(precision, tol, refine):
     nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(16, 16)
@@ -74,12 +74,13 @@ def test_apply_matches_oracle_matvec():
         assert relerr(KHU[r], (K.conj().T @ U[r].ravel()).reshape(U[r].shape)) < 1e-13
 
 
+@pytest.mark.parametrize("refine", ["gmres", "block"])
 @pytest.mark.parametrize("precision,tol", [(64, 1e-13), (32, 1e-12)])
-def test_adjoint_matches_dense(precision, tol):
+def test_adjoint_matches_dense(precision, tol, refine):
     nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(16, 16)
     G = synth.random_rhs(31, 16, 225)
     ref = solvers.solve_dense_adjoint(Mt, Bt, Mx, Ax, G)
-    h = st.fdm_factor(Mt, Bt, Ms, As, 16, precision=precision, tol=tol, max_iter=40)
+    h = st.fdm_factor(Mt, Bt, Ms, As, 16, precision=precision, tol=tol, max_iter=40, refine=refine)
     Lam = to_host(h.solve_adjoint(to_dev(G)))
     assert relerr(Lam, ref) < (1e-12 if precision == 64 else 1e-10)
     # dot test <K^{-1} a, b> = <a, K^{-H} b>
@@ -88,7 +89,7 @@ def test_adjoint_matches_dense(precision, tol):
     assert abs(np.vdot(G, x) - np.vdot(Lam, a)) < 1e-10 * abs(np.vdot(G, x))
 
 
-@pytest.mark.parametrize("refine", ["gmres", "plain"])
+@pytest.mark.parametrize("refine", ["gmres", "plain", "block"])
 def test_no_convergence_is_reported(refine):
     nodes, Mt, Bt, m0, b0, Ms, As, Mx, Ax = system(16, 16)
     h = st.fdm_factor(Mt, Bt, Ms, As, 16, precision=32, tol=1e-15, max_iter=0, refine=refine)
