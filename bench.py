@@ -42,16 +42,32 @@ def kernel_source_hash():
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(precision):
-    """HBM bytes per LDL^T launch from the committed rocprofv3 counter runs, if
-    they were taken on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", "ldlt_c2_fp%d_traffic.json" % precision)
+def measured_traffic(precision, kernel="ldlt"):
+    """HBM bytes per launch of k_ldlt (or k_sweep) from the committed rocprofv3
+    counter runs, if they were taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "%s_c2_fp%d_traffic.json" % (kernel, precision))
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("kernels_hip_sha256_16") != kernel_source_hash():
         return None
     return d.get("bytes_per_launch")
+
+
+def sweep_roofline(reps, n_x, kd, n_t):
+    """HBM roofline of the FP32 sweep (one forward + backward pass over every
+    block, one rhs): algorithmic bytes = the factor slab once per direction,
+    g and u read once and u written twice (complex128); time per launch = the
+    sweep time of a step over its launches (one per application of the
+    inverse)."""
+    slab = n_t * n_x * (kd + 1) * 8
+    alg = 2 * slab + 4 * n_t * n_x * 16
+    launches = sum(r["iterations"] + 1 for r in reps)
+    ms = sum(r["ms_sweeps"] for r in reps) / launches
+    achieved = alg / (ms / 1000.0) / 1e9
+    return {"kernel": "k_sweep (FP32)", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(32, "sweep"), "bytes_per_launch": alg,
+            "ms_per_launch": ms}
 
 
 def progress(msg):
@@ -202,6 +218,7 @@ def main():
         "roofline": {"kernel": "k_ldlt (FP32)", "bound": "mfma", "achieved": achieved,
                      "peak": MFMA_PEAK_TFLOPS[32], "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS[32],
                      "traffic": measured_traffic(32), "flops_per_launch": flops, "ms_per_launch": ms_ldlt},
+        "roofline_sweep": sweep_roofline(reps32, n_x, kd, wl.n_t),
         "stages_ms_fp32": {k: avg(reps32, k) for k in ("ms_eig", "ms_band_fill", "ms_ldlt", "ms_sweeps",
                                                         "ms_transforms", "ms_residual", "ms_factor", "ms_total")},
         "refinement_fp32": {"method": args.refine, "iterations": [r["iterations"] for r in reps32],
