@@ -145,3 +145,26 @@ def test_argument_errors():
     with pytest.raises(_lib.StfemError) as e:
         st.fdm_temporal(wide, np.eye(12))
     assert e.value.status == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus N > 1 exits with a message, before
+    any device work."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_block_refinement_is_accepted_and_unknown_modes_rejected():
+    """refine='block' maps to STFEM_REFINE_BLOCK; other names are refused
+    before the library is called."""
+    assert st.FDM.REFINE == {"gmres": 0, "plain": 1, "block": 2}
+    header = open(os.path.join(ROOT, "include", "stfem.h")).read()
+    assert "STFEM_REFINE_BLOCK = 2" in header
+    Mt = np.eye(2)
+    with pytest.raises(ValueError):
+        st.fdm_factor(Mt, Mt, np.zeros(7), np.zeros(7), 4, refine="bogus")
